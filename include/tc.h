@@ -1,0 +1,176 @@
+/*
+ * tc.h -- binary tensor contractions on AMD Instinct MI355X (gfx950).
+ *
+ * Computes C <- alpha * sum A*B + beta * C for two dense FP64 tensors of any
+ * order, any sets of contracted and free indices and any storage strides.
+ * The operation is the paper's contraction (arXiv:1307.2100, "Towards an
+ * Efficient Use of the BLAS Library for Multilinear Tensor Contractions"):
+ * every index repeated in A and B and absent from C is summed over its whole
+ * range (Sec. 2.3 and Appendix A); alpha and beta follow the BLAS GEMM
+ * definition (Sec. 2.1).  Plans are classified with the paper's Delta-rule
+ * and stride-1 test (Sec. 3.2: Classes 1, 2, 3.1, 3.2) and executed with the
+ * recipe of the class (direct GEMM, COPY+GEMM, GEMV, DOT, GER; Sec. 3.2).
+ *
+ * Conventions shared by every entry point
+ *   - A tensor is described by its rank r and three arrays of r entries:
+ *     extents (int64, >= 0), strides in ELEMENTS (int64, >= 0) and labels
+ *     (int32).  Mode 0 is the first index.  Equal labels name the same index.
+ *   - A label in A and B but not C is contracted; in A and C only, a free
+ *     index of A; in B and C only, a free index of B; in A, B and C, a batch
+ *     index (all three are sliced along it -- an extension, the paper has no
+ *     such index).  Any other placement, or a label repeated inside one
+ *     tensor, is rejected with TC_ERR_LABEL.
+ *   - Host arrays passed to the library are copied; the caller keeps
+ *     ownership of every buffer it passes.  Device buffers (A, B, C,
+ *     workspace) are caller-owned device memory; the library never frees them.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *     Execution is asynchronous on that stream.
+ *   - Errors are reported as tc_status codes only; tc_last_error() returns a
+ *     thread-local message describing the last failure of the calling thread.
+ *     A call that fails at validation writes nothing to C.
+ */
+#ifndef TC_H_
+#define TC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TC_MAX_RANK 16
+#define TC_VERSION "1.0.0"
+
+typedef struct tc_plan_s* tc_plan_t;
+typedef struct tc_batch_s* tc_batch_t;
+
+typedef enum {
+  TC_OK = 0,
+  TC_ERR_INVALID_ARG = 1,      /* null pointer, negative extent or stride, bad option */
+  TC_ERR_LABEL = 2,            /* label repeated in a tensor or summed out of one operand */
+  TC_ERR_EXTENT_MISMATCH = 3,  /* one label with two different extents */
+  TC_ERR_OUTPUT_OVERLAP = 4,   /* C's strides map two entries to one address */
+  TC_ERR_RANK = 5,             /* rank < 0 or > TC_MAX_RANK */
+  TC_ERR_WORKSPACE = 6,        /* workspace smaller than tc_plan_info.workspace_bytes */
+  TC_ERR_UNSUPPORTED = 7,      /* valid request this build does not implement */
+  TC_ERR_HIP = 8,              /* a HIP runtime call failed (message in tc_last_error) */
+  TC_ERR_NOMEM = 9             /* host or device allocation failed */
+} tc_status;
+
+typedef enum {
+  TC_PREC_F64 = 0,             /* FP64 MFMA / FP64 vector arithmetic throughout */
+  TC_PREC_F64_SPLIT_BF16 = 1,  /* FP64 operands split into BF16 slices, BF16 MFMA, FP32 exact chunks, FP64 sum */
+  TC_PREC_F64_SPLIT_FP8 = 2    /* the same with FP8 E4M3 slices */
+} tc_precision;
+
+/* Recipes of Sec. 3.2.  AUTO takes the class's recipe (3.2 -> GEMM, 3.1 ->
+ * COPY_GEMM, 2 -> GEMV, 1 -> DOT, no contracted index -> GER); any other
+ * value forces that recipe, which every class can run (results agree to
+ * rounding; only speed differs). */
+typedef enum {
+  TC_RECIPE_AUTO = 0,
+  TC_RECIPE_GEMM = 1,          /* one strided-gather MFMA GEMM over fused index groups */
+  TC_RECIPE_COPY_GEMM = 2,     /* permute one operand into the workspace, then GEMM */
+  TC_RECIPE_GEMV = 3,          /* matrix-vector products, one per output column */
+  TC_RECIPE_GER = 4,           /* sum over the contracted index of rank-1 updates */
+  TC_RECIPE_DOT = 5            /* one inner product per output entry */
+} tc_recipe;
+
+typedef enum {
+  TC_PICKER_RULES = 0,         /* the paper's recipe for the class, largest index unsliced */
+  TC_PICKER_MLP = 1,           /* learned model (falls back to rules when absent) */
+  TC_PICKER_TUNED = 2          /* autotune cache (falls back to rules when absent) */
+} tc_picker;
+
+typedef struct {
+  tc_precision precision;      /* default TC_PREC_F64 */
+  tc_recipe recipe;            /* default TC_RECIPE_AUTO */
+  tc_picker picker;            /* default TC_PICKER_RULES */
+  int split_slices;            /* slices per operand for split precision; 0 = default */
+  int tile_id;                 /* GEMM tile configuration; -1 = chosen by the picker */
+} tc_options;
+
+typedef struct {
+  int paper_class;             /* 0 (no contracted index), 1, 2, 31 (Class 3.1), 32 (Class 3.2) */
+  tc_recipe recipe;            /* recipe the plan executes */
+  int tile_id;                 /* tile configuration of the GEMM recipes, -1 otherwise */
+  int swapped;                 /* 1 when A and B exchange roles inside the kernels */
+  int copy_operand;            /* COPY_GEMM: 0 copies A, 1 copies B; -1 otherwise */
+  int unit_a, unit_b, unit_c;  /* position of the stride-1 mode of A, B, C (-1: none) */
+  int64_t M, N, K, L;          /* products of free-A, free-B, contracted, batch extents */
+  int nM, nN, nK, nL;          /* modes per group after fusing contiguous modes */
+  double flops;                /* 2 M N K L */
+  double bytes;                /* 8 (|A| + |B| + |C|): algorithmic traffic with beta = 0 */
+  size_t workspace_bytes;      /* device workspace tc_execute needs (0 = none) */
+  tc_precision precision;
+  int split_slices;
+} tc_plan_info;
+
+/* Fills *opt with the defaults listed in tc_options. */
+void tc_options_default(tc_options* opt);
+
+/* Host-only analysis: validates and classifies the contraction and reports
+ * the plan it would build (Sec. 3.1 requirements, Sec. 3.2 classes and
+ * recipes), without touching any GPU.  Arguments as for tc_plan_create;
+ * info must be non-null. */
+tc_status tc_analyze(int rank_a, const int64_t* ext_a, const int64_t* str_a, const int32_t* lab_a,
+                     int rank_b, const int64_t* ext_b, const int64_t* str_b, const int32_t* lab_b,
+                     int rank_c, const int64_t* ext_c, const int64_t* str_c, const int32_t* lab_c,
+                     const tc_options* opt, tc_plan_info* info);
+
+/* Builds an immutable plan for C <- alpha * sum A*B + beta * C (Sec. 2.3;
+ * classification and recipe as in Sec. 3.2).  The plan copies the host
+ * arrays, builds its index-offset tables and uploads them to the current
+ * device.  opt may be NULL for defaults.  On success *out holds a plan the
+ * caller releases with tc_plan_destroy. */
+tc_status tc_plan_create(tc_plan_t* out,
+                         int rank_a, const int64_t* ext_a, const int64_t* str_a, const int32_t* lab_a,
+                         int rank_b, const int64_t* ext_b, const int64_t* str_b, const int32_t* lab_b,
+                         int rank_c, const int64_t* ext_c, const int64_t* str_c, const int32_t* lab_c,
+                         const tc_options* opt);
+
+/* Copies the plan's description into *info. */
+tc_status tc_plan_query(tc_plan_t plan, tc_plan_info* info);
+
+/* Enqueues the contraction on `stream`.  A, B: device pointers to the first
+ * element (index 0 in every mode) of each input; C: device pointer to the
+ * output, read only when beta != 0 (BLAS convention).  workspace: device
+ * memory of at least info.workspace_bytes bytes (may be NULL when that is
+ * 0); it must not be used concurrently by another call.  A plan may run on
+ * several streams at once with distinct workspaces. */
+tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C,
+                     double alpha, double beta, void* workspace, size_t workspace_bytes,
+                     void* stream);
+
+tc_status tc_plan_destroy(tc_plan_t plan);
+
+/* Storage reordering (the copy of Sec. 3.1 F1 / the COPY of COPY+GEMM):
+ * Y[sum_i idx_i * str_y[i]] = X[sum_i idx_i * str_x[i]] for every
+ * multi-index idx over ext[0..rank).  X and Y are device pointers; Y's
+ * addresses must not overlap (checked like C's).  Asynchronous on stream. */
+tc_status tc_permute(int rank, const int64_t* ext, const int64_t* str_x, const int64_t* str_y,
+                     const double* X, double* Y, void* stream);
+
+/* Batches (many independent contractions in one persistent launch).
+ * tc_batch_create takes n plans (FP64, any recipe), which must outlive the
+ * batch.  tc_batch_execute runs C_i <- alpha_i * sum A_i*B_i + beta_i C_i for
+ * all i in one kernel launch; A, B, C, alpha, beta are HOST arrays of n
+ * entries holding device pointers / scalars.  The workspace must hold
+ * tc_batch_workspace() bytes. */
+tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans);
+tc_status tc_batch_workspace(tc_batch_t batch, size_t* bytes);
+tc_status tc_batch_execute(tc_batch_t batch, const double* const* A, const double* const* B,
+                           double* const* C, const double* alpha, const double* beta,
+                           void* workspace, size_t workspace_bytes, void* stream);
+tc_status tc_batch_destroy(tc_batch_t batch);
+
+const char* tc_status_string(tc_status s);
+const char* tc_last_error(void);
+const char* tc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H_ */

@@ -1,0 +1,322 @@
+"""Python binding of libtc, the MI355X tensor-contraction library.
+
+Argument marshalling only: every step of a contraction runs inside libtc
+(host planner in C++, kernels in HIP).  PyTorch supplies device memory and
+streams.  The functions named ``tc_*`` map one-to-one onto the C ABI of
+include/tc.h; ``Plan`` and ``contract`` are thin conveniences over them.
+
+The library is loaded from paper_1307_2100_amd/_lib/libtc.so, built by
+``paper_1307_2100_amd.build.build()``; importing this module without it
+raises ImportError (there is no fallback path).
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libtc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libtc.so is not built (%s); run paper_1307_2100_amd.build.build()" % LIB_PATH)
+
+# PyTorch ships its own HIP runtime (soname libamdhip64.so.7).  Loading torch
+# first makes libtc bind to that same runtime instead of mapping a second
+# copy from /opt/rocm, which would not see the GPU that torch already opened.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+TC_MAX_RANK = 16
+
+# tc_status
+TC_OK = 0
+STATUS_NAMES = ["TC_OK", "TC_ERR_INVALID_ARG", "TC_ERR_LABEL", "TC_ERR_EXTENT_MISMATCH",
+                "TC_ERR_OUTPUT_OVERLAP", "TC_ERR_RANK", "TC_ERR_WORKSPACE", "TC_ERR_UNSUPPORTED",
+                "TC_ERR_HIP", "TC_ERR_NOMEM"]
+for _i, _n in enumerate(STATUS_NAMES):
+    globals()[_n] = _i
+
+# tc_precision
+TC_PREC_F64, TC_PREC_F64_SPLIT_BF16, TC_PREC_F64_SPLIT_FP8 = 0, 1, 2
+PRECISIONS = {"f64": 0, "split_bf16": 1, "split_fp8": 2}
+# tc_recipe
+TC_RECIPE_AUTO, TC_RECIPE_GEMM, TC_RECIPE_COPY_GEMM, TC_RECIPE_GEMV, TC_RECIPE_GER, TC_RECIPE_DOT = range(6)
+RECIPES = {"auto": 0, "gemm": 1, "copy_gemm": 2, "gemv": 3, "ger": 4, "dot": 5}
+RECIPE_NAMES = {v: k for k, v in RECIPES.items()}
+# tc_picker
+TC_PICKER_RULES, TC_PICKER_MLP, TC_PICKER_TUNED = 0, 1, 2
+
+
+class tc_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("recipe", ctypes.c_int), ("picker", ctypes.c_int),
+                ("split_slices", ctypes.c_int), ("tile_id", ctypes.c_int)]
+
+
+class tc_plan_info(ctypes.Structure):
+    _fields_ = [("paper_class", ctypes.c_int), ("recipe", ctypes.c_int), ("tile_id", ctypes.c_int),
+                ("swapped", ctypes.c_int), ("copy_operand", ctypes.c_int),
+                ("unit_a", ctypes.c_int), ("unit_b", ctypes.c_int), ("unit_c", ctypes.c_int),
+                ("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64), ("L", ctypes.c_int64),
+                ("nM", ctypes.c_int), ("nN", ctypes.c_int), ("nK", ctypes.c_int), ("nL", ctypes.c_int),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_size_t), ("precision", ctypes.c_int),
+                ("split_slices", ctypes.c_int)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["recipe_name"] = RECIPE_NAMES.get(self.recipe, "?")
+        return d
+
+
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_DESC = [ctypes.c_int, _I64P, _I64P, _I32P]
+
+_lib.tc_options_default.argtypes = [ctypes.POINTER(tc_options)]
+_lib.tc_options_default.restype = None
+_lib.tc_analyze.argtypes = _DESC * 3 + [ctypes.POINTER(tc_options), ctypes.POINTER(tc_plan_info)]
+_lib.tc_analyze.restype = ctypes.c_int
+_lib.tc_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p)] + _DESC * 3 + [ctypes.POINTER(tc_options)]
+_lib.tc_plan_create.restype = ctypes.c_int
+_lib.tc_plan_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(tc_plan_info)]
+_lib.tc_plan_query.restype = ctypes.c_int
+_lib.tc_execute.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+_lib.tc_execute.restype = ctypes.c_int
+_lib.tc_plan_destroy.argtypes = [ctypes.c_void_p]
+_lib.tc_plan_destroy.restype = ctypes.c_int
+_lib.tc_permute.argtypes = [ctypes.c_int, _I64P, _I64P, _I64P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.tc_permute.restype = ctypes.c_int
+_lib.tc_batch_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+_lib.tc_batch_create.restype = ctypes.c_int
+_lib.tc_batch_workspace.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]
+_lib.tc_batch_workspace.restype = ctypes.c_int
+_lib.tc_batch_execute.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p]
+_lib.tc_batch_execute.restype = ctypes.c_int
+_lib.tc_batch_destroy.argtypes = [ctypes.c_void_p]
+_lib.tc_batch_destroy.restype = ctypes.c_int
+_lib.tc_status_string.argtypes = [ctypes.c_int]
+_lib.tc_status_string.restype = ctypes.c_char_p
+_lib.tc_last_error.restype = ctypes.c_char_p
+_lib.tc_version.restype = ctypes.c_char_p
+
+EXPORTED = ["tc_options_default", "tc_analyze", "tc_plan_create", "tc_plan_query", "tc_execute",
+            "tc_plan_destroy", "tc_permute", "tc_batch_create", "tc_batch_workspace", "tc_batch_execute",
+            "tc_batch_destroy", "tc_status_string", "tc_last_error", "tc_version"]
+
+
+class TCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status, msg))
+        self.status = status
+
+
+def _check(status):
+    if status != TC_OK:
+        raise TCError(status, _lib.tc_last_error().decode())
+
+
+def library_path():
+    return LIB_PATH
+
+
+# ---------------------------------------------------------------- descriptors
+def labels_of(spec):
+    """Labels as int32 codes; a string gives one label per character."""
+    if isinstance(spec, str):
+        return [ord(c) for c in spec]
+    return [int(x) for x in spec]
+
+
+class Desc:
+    """(extents, element strides, labels) of one tensor, as ctypes arrays."""
+
+    def __init__(self, extents, strides, labels):
+        labels = labels_of(labels)
+        if not (len(extents) == len(strides) == len(labels)):
+            raise ValueError("extents, strides and labels differ in length")
+        self.rank = len(labels)
+        n = max(1, self.rank)
+        self.ext = (ctypes.c_int64 * n)(*[int(e) for e in extents])
+        self.str = (ctypes.c_int64 * n)(*[int(s) for s in strides])
+        self.lab = (ctypes.c_int32 * n)(*labels)
+
+    def args(self):
+        return [self.rank, self.ext, self.str, self.lab]
+
+    @classmethod
+    def of_tensor(cls, t, labels):
+        return cls(list(t.shape), list(t.stride()), labels)
+
+
+def make_options(precision="f64", recipe="auto", picker=0, split_slices=0, tile_id=-1):
+    o = tc_options()
+    _lib.tc_options_default(ctypes.byref(o))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.recipe = RECIPES[recipe] if isinstance(recipe, str) else int(recipe)
+    o.picker = int(picker)
+    o.split_slices = int(split_slices)
+    o.tile_id = int(tile_id)
+    return o
+
+
+# ------------------------------------------------------------ C ABI wrappers
+def tc_options_default():
+    o = tc_options()
+    _lib.tc_options_default(ctypes.byref(o))
+    return o
+
+
+def tc_analyze(dA, dB, dC, options=None):
+    info = tc_plan_info()
+    _check(_lib.tc_analyze(*dA.args(), *dB.args(), *dC.args(),
+                           ctypes.byref(options) if options is not None else None, ctypes.byref(info)))
+    return info
+
+
+def tc_plan_create(dA, dB, dC, options=None):
+    h = ctypes.c_void_p()
+    _check(_lib.tc_plan_create(ctypes.byref(h), *dA.args(), *dB.args(), *dC.args(),
+                               ctypes.byref(options) if options is not None else None))
+    return h
+
+
+def tc_plan_query(plan):
+    info = tc_plan_info()
+    _check(_lib.tc_plan_query(plan, ctypes.byref(info)))
+    return info
+
+
+def tc_execute(plan, A_ptr, B_ptr, C_ptr, alpha, beta, ws_ptr, ws_bytes, stream):
+    _check(_lib.tc_execute(plan, A_ptr, B_ptr, C_ptr, float(alpha), float(beta), ws_ptr, int(ws_bytes), stream))
+
+
+def tc_plan_destroy(plan):
+    _check(_lib.tc_plan_destroy(plan))
+
+
+def tc_permute(extents, strides_x, strides_y, X_ptr, Y_ptr, stream):
+    n = max(1, len(extents))
+    e = (ctypes.c_int64 * n)(*[int(v) for v in extents])
+    sx = (ctypes.c_int64 * n)(*[int(v) for v in strides_x])
+    sy = (ctypes.c_int64 * n)(*[int(v) for v in strides_y])
+    _check(_lib.tc_permute(len(extents), e, sx, sy, X_ptr, Y_ptr, stream))
+
+
+def tc_status_string(status):
+    return _lib.tc_status_string(int(status)).decode()
+
+
+def tc_last_error():
+    return _lib.tc_last_error().decode()
+
+
+def tc_version():
+    return _lib.tc_version().decode()
+
+
+# ---------------------------------------------------------------- torch side
+def _torch():
+    import torch  # device memory and streams only
+    return torch
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require_f64_cuda(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError("%s must be a float64 CUDA (HIP) tensor" % name)
+
+
+class Plan:
+    """A libtc plan for fixed extents, strides and labels of A, B and C."""
+
+    def __init__(self, dA, dB, dC, precision="f64", recipe="auto", tile_id=-1, split_slices=0, picker=0):
+        self.options = make_options(precision, recipe, picker, split_slices, tile_id)
+        self.handle = tc_plan_create(dA, dB, dC, self.options)
+        self.info = tc_plan_query(self.handle)
+        self._ws = None
+
+    @classmethod
+    def for_tensors(cls, A, labA, B, labB, C, labC, **kw):
+        return cls(Desc.of_tensor(A, labA), Desc.of_tensor(B, labB), Desc.of_tensor(C, labC), **kw)
+
+    def workspace(self, device=None):
+        nbytes = self.info.workspace_bytes
+        if nbytes == 0:
+            return None
+        torch = _torch()
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+        return self._ws
+
+    def execute(self, A, B, C, alpha=1.0, beta=0.0, stream=None, workspace=None):
+        _require_f64_cuda(A, "A")
+        _require_f64_cuda(B, "B")
+        _require_f64_cuda(C, "C")
+        ws = workspace if workspace is not None else self.workspace(C.device)
+        wptr = ctypes.c_void_p(ws.data_ptr()) if ws is not None else None
+        wbytes = ws.numel() * ws.element_size() if ws is not None else 0
+        tc_execute(self.handle, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                   ctypes.c_void_p(C.data_ptr()), alpha, beta, wptr, wbytes, _stream_handle(stream))
+        return C
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            tc_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def output_shape(A, labA, B, labB, labC):
+    ext = {}
+    for l, e in zip(labels_of(labA), A.shape):
+        ext[l] = e
+    for l, e in zip(labels_of(labB), B.shape):
+        ext[l] = e
+    return [ext[l] for l in labels_of(labC)]
+
+
+def empty_colmajor(shape, device="cuda"):
+    """An uninitialised FP64 tensor stored column-major (first index stride 1)."""
+    torch = _torch()
+    if len(shape) == 0:
+        return torch.empty((), dtype=torch.float64, device=device)
+    return torch.empty(list(reversed(shape)), dtype=torch.float64, device=device).permute(
+        *reversed(range(len(shape))))
+
+
+def contract(A, labA, B, labB, labC, C=None, alpha=1.0, beta=0.0, **plan_kw):
+    """C <- alpha * sum A*B + beta * C on the GPU (C allocated column-major when None)."""
+    if C is None:
+        C = empty_colmajor(output_shape(A, labA, B, labB, labC), device=A.device)
+        beta = 0.0
+    plan = Plan.for_tensors(A, labA, B, labB, C, labC, **plan_kw)
+    try:
+        plan.execute(A, B, C, alpha, beta)
+    finally:
+        # the plan's offset tables and workspace must outlive the kernels
+        _torch().cuda.current_stream().synchronize()
+        plan.close()
+    return C
+
+
+def permute(X, strides_out, Y):
+    """Y[sum idx*strides_out] = X[idx] on the GPU (Y a flat FP64 CUDA tensor)."""
+    _require_f64_cuda(X, "X")
+    _require_f64_cuda(Y, "Y")
+    tc_permute(list(X.shape), list(X.stride()), list(strides_out), ctypes.c_void_p(X.data_ptr()),
+               ctypes.c_void_p(Y.data_ptr()), _stream_handle())
+    return Y

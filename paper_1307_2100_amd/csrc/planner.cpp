@@ -1,0 +1,379 @@
+// Host planner: validation, normalisation, the paper's classification and
+// the layout of index groups for the kernels.
+//
+// Classification follows Sec. 3.2 of the paper: with p contracted indices,
+// Delta(t) = N(t) - p counts the free indices of each input; Class 1 has no
+// free index in either, Class 2 in exactly one, Class 3 in both.  Class 3
+// splits on the stride-1 modes (Sec. 3.2, "Class 3.1" / "Class 3.2"): when
+// the two inputs' stride-1 modes are different contracted indices no slicing
+// meets R1-R3 of Sec. 3.1 and GEMM needs a copy first (3.1); otherwise a
+// direct GEMM exists (3.2).  Readings where the paper is silent: extent-1
+// modes are dropped before classifying; batch indices (in A, B and C) are
+// sliced everywhere and not counted in N(t); an input with no stride-1 mode,
+// or whose stride-1 mode is a batch index, cannot meet R1 (Class 3.1); p = 0
+// (an outer product) is reported as class 0.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+namespace tc {
+namespace {
+
+struct LabelInfo {
+  int32_t label;
+  int64_t ext;
+  int pos[3];  // position in A, B, C (-1 if absent)
+};
+
+int find_label(const TensorDesc& t, int32_t l) {
+  for (int i = 0; i < t.rank; ++i)
+    if (t.lab[i] == l) return i;
+  return -1;
+}
+
+std::string fmt(const char* f, long long a = 0, long long b = 0) {
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), f, a, b);
+  return buf;
+}
+
+// Output entries must not alias: after sorting the modes of extent > 1 by
+// stride, each stride must be positive and reach past the span of the
+// previous ones.  (A sufficient test; it rejects some exotic injective layouts.)
+bool output_overlaps(const TensorDesc& C) {
+  std::vector<std::pair<int64_t, int64_t>> m;  // (stride, extent)
+  for (int i = 0; i < C.rank; ++i) {
+    if (C.ext[i] == 0) return false;  // empty: nothing is written
+    if (C.ext[i] > 1) m.push_back({C.str[i], C.ext[i]});
+  }
+  std::sort(m.begin(), m.end());
+  int64_t span = 1;  // entries covered by the modes so far
+  for (auto& se : m) {
+    if (se.first <= 0 || se.first < span) return true;
+    span = se.first * se.second;
+  }
+  return false;
+}
+
+TensorDesc squeeze(const TensorDesc& t) {
+  TensorDesc s;
+  for (int i = 0; i < t.rank; ++i) {
+    if (t.ext[i] == 1) continue;
+    s.ext[s.rank] = t.ext[i];
+    s.str[s.rank] = t.str[i];
+    s.lab[s.rank] = t.lab[i];
+    s.rank++;
+  }
+  return s;
+}
+
+int unit_mode(const TensorDesc& t) {
+  for (int i = 0; i < t.rank; ++i)
+    if (t.str[i] == 1 && t.ext[i] > 1) return i;
+  return -1;
+}
+
+// Sort a group's modes by the strides of one slot (ties: the next slot's),
+// so that the slot whose stride-1 mode lives in the group reads it first.
+void order_group(Group& g, int key, int tie) {
+  std::vector<int> idx(g.n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    if (g.str[key][a] != g.str[key][b]) return g.str[key][a] < g.str[key][b];
+    return g.str[tie][a] < g.str[tie][b];
+  });
+  Group o = g;
+  for (int i = 0; i < g.n; ++i) {
+    o.ext[i] = g.ext[idx[i]];
+    o.lab[i] = g.lab[idx[i]];
+    for (int s = 0; s < 3; ++s) o.str[s][i] = g.str[s][idx[i]];
+  }
+  g = o;
+}
+
+// Merge neighbouring modes that every holder of the group stores
+// contiguously one after the other (stride of the next = stride * extent).
+void fuse_group(Group& g, const bool holders[3]) {
+  if (g.n <= 1) return;
+  Group o;
+  o.n = 0;
+  for (int i = 0; i < g.n; ++i) {
+    bool merge = o.n > 0;
+    if (merge) {
+      for (int s = 0; s < 3; ++s)
+        if (holders[s] && g.str[s][i] != o.str[s][o.n - 1] * o.ext[o.n - 1]) merge = false;
+    }
+    if (merge) {
+      o.ext[o.n - 1] *= g.ext[i];
+    } else {
+      o.ext[o.n] = g.ext[i];
+      o.lab[o.n] = g.lab[i];
+      for (int s = 0; s < 3; ++s) o.str[s][o.n] = g.str[s][i];
+      o.n++;
+    }
+  }
+  g = o;
+}
+
+int64_t product(const TensorDesc& t) {
+  int64_t p = 1;
+  for (int i = 0; i < t.rank; ++i) p *= t.ext[i];
+  return p;
+}
+
+// Rule picker for the GEMM tile: the largest tile that still gives the chip
+// (256 compute units) a few workgroups each.
+int pick_tile(int64_t M, int64_t N, int64_t L) {
+  auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * L; };
+  if (tiles(128, 128) >= 512) return 0;
+  if (M >= N && tiles(128, 64) >= 512) return 2;
+  if (N > M && tiles(64, 128) >= 512) return 3;
+  return 1;
+}
+
+}  // namespace
+
+int paper_class(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, int unitA, int unitB) {
+  int p = 0, batchA = 0, batchB = 0;
+  auto is_batch = [&](int32_t l) { return find_label(A, l) >= 0 && find_label(B, l) >= 0 && find_label(C, l) >= 0; };
+  for (int i = 0; i < A.rank; ++i) {
+    if (is_batch(A.lab[i])) {
+      batchA++;
+    } else if (find_label(B, A.lab[i]) >= 0) {
+      p++;
+    }
+  }
+  for (int i = 0; i < B.rank; ++i)
+    if (is_batch(B.lab[i])) batchB++;
+  int dA = A.rank - batchA - p, dB = B.rank - batchB - p;
+  if (p == 0) return 0;
+  if (dA == 0 && dB == 0) return 1;
+  if (dA == 0 || dB == 0) return 2;
+  if (unitA < 0 || unitB < 0) return 31;
+  int32_t ua = A.lab[unitA], ub = B.lab[unitB];
+  if (is_batch(ua) || is_batch(ub)) return 31;
+  bool ua_con = find_label(B, ua) >= 0;
+  bool ub_con = find_label(A, ub) >= 0;
+  if (ua != ub && ua_con && ub_con) return 31;
+  return 32;
+}
+
+tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& C0, const tc_options& opt,
+                  Analysis* out, std::string* err) {
+  Analysis an;
+  const TensorDesc* T[3] = {&A0, &B0, &C0};
+  const char* name[3] = {"A", "B", "C"};
+  for (int s = 0; s < 3; ++s) {
+    const TensorDesc& t = *T[s];
+    if (t.rank < 0 || t.rank > TC_MAX_RANK) {
+      *err = std::string("rank of ") + name[s] + fmt(" is %lld (allowed 0..%lld)", t.rank, TC_MAX_RANK);
+      return TC_ERR_RANK;
+    }
+    for (int i = 0; i < t.rank; ++i) {
+      if (t.ext[i] < 0) {
+        *err = std::string("negative extent in ") + name[s] + fmt(" mode %lld", i);
+        return TC_ERR_INVALID_ARG;
+      }
+      if (t.str[i] < 0) {
+        *err = std::string("negative stride in ") + name[s] + fmt(" mode %lld", i);
+        return TC_ERR_INVALID_ARG;
+      }
+      for (int j = 0; j < i; ++j)
+        if (t.lab[j] == t.lab[i]) {
+          *err = std::string("label repeated within ") + name[s] + fmt(" (label %lld)", t.lab[i]);
+          return TC_ERR_LABEL;
+        }
+    }
+  }
+  if (opt.precision < TC_PREC_F64 || opt.precision > TC_PREC_F64_SPLIT_FP8 || opt.recipe < TC_RECIPE_AUTO ||
+      opt.recipe > TC_RECIPE_DOT || opt.tile_id < -1 || opt.tile_id > 3 || opt.split_slices < 0 ||
+      opt.split_slices > 8) {
+    *err = "invalid tc_options field";
+    return TC_ERR_INVALID_ARG;
+  }
+  // Every label: in A and B (contracted), A and C, B and C, or all three.
+  for (int s = 0; s < 3; ++s) {
+    const TensorDesc& t = *T[s];
+    for (int i = 0; i < t.rank; ++i) {
+      int in = 0;
+      for (int u = 0; u < 3; ++u) {
+        int j = find_label(*T[u], t.lab[i]);
+        if (j >= 0) {
+          in++;
+          if (T[u]->ext[j] != t.ext[i]) {
+            *err = fmt("label %lld has extents %lld", t.lab[i], t.ext[i]) + fmt(" and %lld", T[u]->ext[j]);
+            return TC_ERR_EXTENT_MISMATCH;
+          }
+        }
+      }
+      if (in < 2) {
+        *err = fmt("label %lld appears only in ", t.lab[i]) + name[s] +
+               " (a contraction sums an index shared by both inputs)";
+        return TC_ERR_LABEL;
+      }
+    }
+  }
+  if (output_overlaps(C0)) {
+    *err = "output strides overlap (two entries of C would share an address)";
+    return TC_ERR_OUTPUT_OVERLAP;
+  }
+
+  tc_plan_info& info = an.info;
+  info.precision = opt.precision;
+  info.split_slices = opt.split_slices;
+  info.copy_operand = -1;
+  info.tile_id = -1;
+  info.unit_a = unit_mode(A0);
+  info.unit_b = unit_mode(B0);
+  info.unit_c = unit_mode(C0);
+
+  for (int i = 0; i < C0.rank; ++i)
+    if (C0.ext[i] == 0) an.empty_out = true;
+  for (int i = 0; i < A0.rank; ++i)
+    if (A0.ext[i] == 0 && find_label(B0, A0.lab[i]) >= 0 && find_label(C0, A0.lab[i]) < 0) an.empty_sum = true;
+
+  TensorDesc A = squeeze(A0), B = squeeze(B0), C = squeeze(C0);
+  int ua = unit_mode(A), ub = unit_mode(B);
+  info.paper_class = paper_class(A, B, C, ua, ub);
+
+  tc_recipe recipe = opt.recipe;
+  if (recipe == TC_RECIPE_AUTO) {
+    switch (info.paper_class) {
+      case 32: recipe = TC_RECIPE_GEMM; break;
+      case 31: recipe = TC_RECIPE_COPY_GEMM; break;
+      case 2: recipe = TC_RECIPE_GEMV; break;
+      case 1: recipe = TC_RECIPE_DOT; break;
+      default: recipe = TC_RECIPE_GER; break;
+    }
+  }
+  info.recipe = recipe;
+
+  // The kernels write C along their column index with consecutive lanes, so
+  // C's stride-1 mode belongs in the column group: exchange the inputs when
+  // it is a free index of A (the result does not depend on the operand
+  // order, Sec. 2.3 footnote).
+  int uc = unit_mode(C);
+  bool swap = false;
+  if (uc >= 0) {
+    int32_t l = C.lab[uc];
+    swap = find_label(A, l) >= 0 && find_label(B, l) < 0;
+  }
+  info.swapped = swap ? 1 : 0;
+  const TensorDesc& KA = swap ? B : A;
+  const TensorDesc& KB = swap ? A : B;
+  an.elems[SA] = product(KA);
+  an.elems[SB] = product(KB);
+  an.elems[SC] = product(C);
+
+  // Distribute the modes over the four groups.
+  Group* G = an.g;
+  for (int gi = 0; gi < 4; ++gi) G[gi] = Group();
+  auto add = [&](int gi, int32_t lab, int64_t ext, int64_t sa, int64_t sb, int64_t sc) {
+    Group& g = G[gi];
+    g.lab[g.n] = lab;
+    g.ext[g.n] = ext;
+    g.str[SA][g.n] = sa;
+    g.str[SB][g.n] = sb;
+    g.str[SC][g.n] = sc;
+    g.n++;
+  };
+  for (int i = 0; i < KA.rank; ++i) {
+    int jb = find_label(KB, KA.lab[i]), jc = find_label(C, KA.lab[i]);
+    if (jb >= 0 && jc >= 0)
+      add(GL, KA.lab[i], KA.ext[i], KA.str[i], KB.str[jb], C.str[jc]);
+    else if (jb >= 0)
+      add(GK, KA.lab[i], KA.ext[i], KA.str[i], KB.str[jb], 0);
+    else
+      add(GM, KA.lab[i], KA.ext[i], KA.str[i], 0, C.str[jc]);
+  }
+  for (int i = 0; i < KB.rank; ++i) {
+    if (find_label(KA, KB.lab[i]) >= 0) continue;
+    int jc = find_label(C, KB.lab[i]);
+    add(GN, KB.lab[i], KB.ext[i], 0, KB.str[i], C.str[jc]);
+  }
+
+  auto unit_in = [&](const Group& g, int slot) {
+    for (int i = 0; i < g.n; ++i)
+      if (g.str[slot][i] == 1) return true;
+    return false;
+  };
+
+  // COPY_GEMM: copy the input with fewer entries (ties: kernel B) into a
+  // packed layout [its free group, contracted group, batch group].
+  if (recipe == TC_RECIPE_COPY_GEMM) an.copy_slot = an.elems[SA] < an.elems[SB] ? SA : SB;
+  info.copy_operand = an.copy_slot < 0 ? -1 : ((an.copy_slot == SA) != swap ? 0 : 1);
+
+  order_group(G[GM], SA, SC);
+  if (unit_in(G[GN], SB))
+    order_group(G[GN], SB, SC);
+  else
+    order_group(G[GN], SC, SB);
+  {
+    int key = SA;
+    bool a_unit = unit_in(G[GK], SA) && an.copy_slot != SA;
+    bool b_unit = unit_in(G[GK], SB) && an.copy_slot != SB;
+    if (!a_unit && b_unit) key = SB;
+    if (an.copy_slot == SA) key = SB;
+    order_group(G[GK], key, key == SA ? SB : SA);
+  }
+  order_group(G[GL], SC, SA);
+
+  if (an.copy_slot >= 0) {
+    int cs = an.copy_slot;
+    int free_g = cs == SA ? GM : GN;
+    const TensorDesc& X = cs == SA ? KA : KB;
+    // packed strides per label in group order
+    int64_t stride = 1;
+    int32_t labs[TC_MAX_RANK];
+    int64_t dst[TC_MAX_RANK];
+    int nl = 0;
+    for (int gi : {free_g, (int)GK, (int)GL}) {
+      Group& g = G[gi];
+      for (int i = 0; i < g.n; ++i) {
+        g.str[cs][i] = stride;
+        labs[nl] = g.lab[i];
+        dst[nl] = stride;
+        nl++;
+        stride *= g.ext[i];
+      }
+    }
+    an.copy_rank = X.rank;
+    for (int i = 0; i < X.rank; ++i) {
+      an.copy_ext[i] = X.ext[i];
+      an.copy_src_str[i] = X.str[i];
+      an.copy_dst_str[i] = 0;
+      for (int q = 0; q < nl; ++q)
+        if (labs[q] == X.lab[i]) an.copy_dst_str[i] = dst[q];
+    }
+    info.workspace_bytes = (size_t)an.elems[cs] * sizeof(double);
+  }
+
+  const bool hold[4][3] = {{true, false, true}, {false, true, true}, {true, true, false}, {true, true, true}};
+  for (int gi = 0; gi < 4; ++gi) fuse_group(G[gi], hold[gi]);
+
+  bool a_mfast = G[GM].n > 0 && G[GM].str[SA][0] == 1;
+  bool b_nfast = G[GN].n > 0 && G[GN].str[SB][0] == 1;
+  an.a_kfast = !a_mfast && G[GK].n > 0 && G[GK].str[SA][0] == 1;
+  an.b_kfast = !b_nfast && G[GK].n > 0 && G[GK].str[SB][0] == 1;
+
+  info.M = G[GM].size();
+  info.N = G[GN].size();
+  info.K = G[GK].size();
+  info.L = G[GL].size();
+  if (an.empty_out) info.M = info.N = info.L = 0;
+  info.nM = G[GM].n;
+  info.nN = G[GN].n;
+  info.nK = G[GK].n;
+  info.nL = G[GL].n;
+  info.flops = 2.0 * (double)info.M * (double)info.N * (double)info.K * (double)info.L;
+  info.bytes = 8.0 * ((double)product(A0) + (double)product(B0) + (double)product(C0));
+  if (recipe == TC_RECIPE_GEMM || recipe == TC_RECIPE_COPY_GEMM)
+    info.tile_id = opt.tile_id >= 0 ? opt.tile_id : pick_tile(info.M, info.N, info.L);
+  *out = an;
+  return TC_OK;
+}
+
+}  // namespace tc

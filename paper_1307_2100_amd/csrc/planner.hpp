@@ -1,0 +1,79 @@
+// Host-side planner: validation, normalisation, the paper's classification
+// and the index-group layout the kernels consume.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tc.h"
+
+namespace tc {
+
+// One tensor as given by the caller (extents, element strides, labels).
+struct TensorDesc {
+  int rank = 0;
+  int64_t ext[TC_MAX_RANK] = {};
+  int64_t str[TC_MAX_RANK] = {};
+  int32_t lab[TC_MAX_RANK] = {};
+};
+
+// Operand slots inside a group: the two inputs in kernel roles and the output.
+enum Slot { SA = 0, SB = 1, SC = 2 };
+
+// Index groups: free indices of the kernel's A (rows), free indices of the
+// kernel's B (columns), contracted indices, batch indices.
+enum GroupId { GM = 0, GN = 1, GK = 2, GL = 3 };
+
+// An ordered list of modes sharing one role.  The group's linear index g
+// decodes column-major over the modes (mode 0 fastest); each operand holding
+// the group has the stride of every mode (0 where it lacks the mode).
+struct Group {
+  int n = 0;
+  int64_t ext[TC_MAX_RANK] = {};
+  int64_t str[3][TC_MAX_RANK] = {};
+  int32_t lab[TC_MAX_RANK] = {};
+  int64_t size() const {
+    int64_t s = 1;
+    for (int i = 0; i < n; ++i) s *= ext[i];
+    return s;
+  }
+  // Offset of linear index g for operand slot `slot`.
+  int64_t offset(int slot, int64_t g) const {
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+      int64_t v = g % ext[i];
+      g /= ext[i];
+      off += v * str[slot][i];
+    }
+    return off;
+  }
+};
+
+struct Analysis {
+  tc_plan_info info{};
+  Group g[4];
+  bool empty_out = false;   // some extent of C is 0: nothing to compute
+  bool empty_sum = false;   // some contracted extent is 0: C <- beta * C
+  bool a_kfast = false;     // kernel A's stride-1 mode leads the contracted group
+  bool b_kfast = false;     // kernel B's stride-1 mode leads the contracted group
+  int64_t elems[3] = {};    // entries of kernel A, kernel B, C (products of extents)
+  // COPY_GEMM: the copied operand (kernel slot) and its modes before and after
+  // the copy, in the copied tensor's own storage order.
+  int copy_slot = -1;
+  int copy_rank = 0;
+  int64_t copy_ext[TC_MAX_RANK] = {};
+  int64_t copy_src_str[TC_MAX_RANK] = {};
+  int64_t copy_dst_str[TC_MAX_RANK] = {};
+};
+
+// Validates, classifies (Sec. 3.2) and lays out the contraction.  On error
+// returns the status and writes a message to *err.
+tc_status analyze(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, const tc_options& opt,
+                  Analysis* out, std::string* err);
+
+// The paper's class (0, 1, 2, 31, 32) from labels and stride-1 positions of
+// the two inputs after normalisation (exposed for tests through tc_analyze).
+int paper_class(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, int unitA, int unitB);
+
+}  // namespace tc

@@ -1,0 +1,211 @@
+"""Host-side tests of the C ABI: the library loads and exports every symbol
+include/tc.h declares, the planner's classification agrees with the
+brute-force slicing oracle, argument errors come back as status codes, and
+the plan's accounting matches the paper's worked numbers.  No GPU needed:
+only tc_analyze and the error paths are called."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1307_2100_amd as tc
+import synth
+from oracle import slicing
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tc.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:tc_status|void|const char\s*\*)\s*(tc_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    declared = header_functions()
+    assert "tc_plan_create" in declared and "tc_execute" in declared
+    out = subprocess.run(["nm", "-D", "--defined-only", tc.library_path()], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s(tc_\w+)$", out, re.M))
+    missing = [f for f in declared if f not in exported]
+    assert not missing, missing
+    assert sorted(tc.EXPORTED) == declared
+    assert tc.tc_version() == "1.0.0"
+
+
+def colmajor_strides(shape):
+    st, acc = [], 1
+    for e in shape:
+        st.append(acc)
+        acc *= e
+    return st
+
+
+def desc(labels, ext, strides=None):
+    shape = [ext[l] for l in labels]
+    return tc.Desc(shape, strides if strides is not None else colmajor_strides(shape), labels)
+
+
+def analyze(labA, labB, labC, ext, sA=None, sB=None, sC=None, **opt):
+    return tc.tc_analyze(desc(labA, ext, sA), desc(labB, ext, sB), desc(labC, ext, sC),
+                         tc.make_options(**opt) if opt else None)
+
+
+def test_paper_class_examples():
+    import json
+    fx = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_slicings.json")))
+    for c in fx["classes"]:
+        ext = {l: 3 for l in c["T"] + c["S"]}
+        info = analyze(c["T"], c["S"], c["R"], ext)
+        assert info.paper_class == c["class"], c["where"]
+
+
+def test_paper_recipes_by_class():
+    ext = {l: 4 for l in "abghij"}
+    assert analyze("abg", "hbg", "ah", ext).recipe == tc.TC_RECIPE_GEMM          # 3.2
+    assert analyze("abg", "gah", "bh", ext).recipe == tc.TC_RECIPE_COPY_GEMM     # 3.1
+    assert analyze("abg", "bg", "a", ext).recipe == tc.TC_RECIPE_GEMV            # 2
+    assert analyze("abg", "abg", "", ext).recipe == tc.TC_RECIPE_DOT             # 1
+    assert analyze("ab", "gh", "abgh", ext).recipe == tc.TC_RECIPE_GER           # outer product
+    info = analyze("abg", "gah", "bh", ext, recipe="gemm")
+    assert info.recipe == tc.TC_RECIPE_GEMM and info.paper_class == 31
+
+
+def test_classifier_agrees_with_slicing_oracle_on_random_shapes():
+    """The planner's stride-1 rule against brute-force R1-R3 enumeration on
+    random contractions with random storage orders (including strided and
+    stride-1-free layouts)."""
+    g = np.random.default_rng(99)
+    seen = set()
+    for _ in range(1500):
+        la, lb, lc, ext = synth.random_contraction(g, rank_range=(1, 5), ext_range=(2, 4),
+                                                   max_elems=10 ** 9, p_outer=0.05, allow_batch=True)
+        strides = {}
+        units = {}
+        for name, labs in (("A", la), ("B", lb)):
+            order = list(g.permutation(len(labs)))
+            st = [0] * len(labs)
+            acc = 1 if g.random() > 0.05 else 2      # sometimes no stride-1 mode at all
+            for pos in order:
+                st[pos] = acc
+                acc *= ext[labs[pos]]
+            strides[name] = st
+            units[name] = st.index(1) if 1 in st else None
+        info = analyze(la, lb, lc, ext, sA=strides["A"], sB=strides["B"])
+        want = slicing.classify(la, lb, units["A"], units["B"], lc)
+        assert info.paper_class == want, (la, lb, lc, strides)
+        seen.add(want)
+    assert seen == {0, 1, 2, 31, 32}
+
+
+def test_table_new3d_through_the_planner():
+    ext = {l: 5 for l in "abgh"}
+    counts = {31: 0, 32: 0}
+    for con in (("b", "g"), ("a", "g"), ("a", "b")):
+        free_a = [l for l in "abg" if l not in con][0]
+        for order in (con, con[::-1]):
+            for pos in (2, 1, 0):
+                lb = list(order)
+                lb.insert(pos, "h")
+                info = analyze("abg", "".join(lb), free_a + "h", ext)
+                counts[info.paper_class] += 1
+    assert counts == {31: 4, 32: 14}
+
+
+@pytest.mark.parametrize("bad,status", [
+    (("aa", "ab", "b"), "TC_ERR_LABEL"),
+    (("ab", "cd", "ad"), "TC_ERR_LABEL"),
+    (("ab", "bc", "acd"), "TC_ERR_LABEL"),
+])
+def test_label_errors(bad, status):
+    ext = {l: 3 for l in "abcd"}
+    with pytest.raises(tc.TCError) as e:
+        analyze(*bad, ext)
+    assert tc.STATUS_NAMES[e.value.status] == status
+    assert tc.tc_last_error()
+
+
+def test_extent_overlap_rank_errors():
+    with pytest.raises(tc.TCError) as e:
+        tc.tc_analyze(tc.Desc([3, 4], [1, 3], "ik"), tc.Desc([5, 2], [1, 5], "kj"), tc.Desc([3, 2], [1, 3], "ij"))
+    assert e.value.status == tc.TC_ERR_EXTENT_MISMATCH
+    with pytest.raises(tc.TCError) as e:   # C rows and columns share addresses
+        tc.tc_analyze(tc.Desc([3, 4], [1, 3], "ik"), tc.Desc([4, 2], [1, 4], "kj"), tc.Desc([3, 2], [1, 2], "ij"))
+    assert e.value.status == tc.TC_ERR_OUTPUT_OVERLAP
+    with pytest.raises(tc.TCError) as e:
+        tc.tc_analyze(tc.Desc([3, 4], [-1, 3], "ik"), tc.Desc([4, 2], [1, 4], "kj"), tc.Desc([3, 2], [1, 3], "ij"))
+    assert e.value.status == tc.TC_ERR_INVALID_ARG
+    big = "abcdefghijklmnopq"
+    with pytest.raises(tc.TCError) as e:
+        tc.tc_analyze(tc.Desc([1] * 17, [1] * 17, big), tc.Desc([1], [1], "a"), tc.Desc([1] * 16, [1] * 16, big[1:]))
+    assert e.value.status == tc.TC_ERR_RANK
+    with pytest.raises(tc.TCError) as e:
+        analyze("ik", "kj", "ij", {"i": 2, "k": 2, "j": 2}, recipe=9)
+    assert e.value.status == tc.TC_ERR_INVALID_ARG
+
+
+def test_execute_rejects_null_plan_and_small_workspace_without_gpu():
+    with pytest.raises(tc.TCError) as e:
+        tc.tc_execute(None, None, None, None, 1.0, 0.0, None, 0, None)
+    assert e.value.status == tc.TC_ERR_INVALID_ARG
+
+
+def test_group_sizes_fusion_and_flops():
+    labA, labB, labC, ext = synth.workload_cc_a(128, 32)
+    info = analyze(labA, labB, labC, ext)
+    # C's stride-1 index a is free in A, so the kernel takes B as its A
+    assert info.swapped == 1
+    assert (info.M, info.N, info.K, info.L) == (32 * 32, 128 * 128, 128 * 128, 1)
+    assert (info.nM, info.nN, info.nK) == (1, 1, 1)      # every group fuses to one mode
+    assert info.flops == 549755813888.0
+    assert info.bytes == 8 * (128 ** 4 + 2 * 128 ** 2 * 32 ** 2)
+    labA, labB, labC, ext = synth.workload_cc_b(128, 32)
+    info = analyze(labA, labB, labC, ext)
+    assert info.paper_class == 32 and info.recipe == tc.TC_RECIPE_GEMM
+    assert (info.nM, info.nN, info.nK) == (2, 2, 2)      # (b,j), (a,i), (k,c) do not fuse
+    assert info.flops == 137438953472.0
+
+
+def test_equal_operation_counts_paper_footnotes():
+    """Sec. 4.1 footnote: the two 3-D contractions do the same arithmetic;
+    Sec. 4.2 footnote: so do the two coupled-cluster ones."""
+    ext = {l: 7 for l in "abgh"}
+    assert analyze("abg", "hbg", "ah", ext).flops == analyze("abg", "gah", "bh", ext).flops
+    ext = {"i": 9, "j": 9, "a": 3, "b": 4, "g": 5, "d": 6}
+    assert analyze("iajb", "igjd", "abgd", ext).flops == analyze("iajb", "jgid", "abgd", ext).flops
+
+
+def test_memory_size_worked_example():
+    """Sec. 4.2: X^{i a j b} with a = b = 80 and i = j = 2000 takes 204 GB in FP64."""
+    ext = {"i": 2000, "j": 2000, "a": 80, "b": 80, "g": 80, "d": 80}
+    info = analyze("iajb", "igjd", "abgd", ext)
+    x_bytes = 8 * 2000 * 2000 * 80 * 80
+    assert x_bytes == 204_800_000_000
+    assert info.bytes == 2 * x_bytes + 8 * 80 ** 4
+
+
+def test_copy_recipe_workspace_and_operand():
+    ext = {l: 6 for l in "abgh"}
+    info = analyze("abg", "gah", "bh", ext)
+    assert info.recipe == tc.TC_RECIPE_COPY_GEMM
+    assert info.workspace_bytes == 8 * 6 ** 3 and info.copy_operand in (0, 1)
+    ext2 = dict(ext, h=3)        # B smaller: B is copied
+    assert analyze("abg", "gah", "bh", ext2).copy_operand == 1
+
+
+def test_empty_and_degenerate_shapes_analyze():
+    info = analyze("ik", "kj", "ij", {"i": 0, "k": 3, "j": 2})
+    assert info.M == 0 and info.flops == 0
+    info = analyze("ik", "kj", "ij", {"i": 4, "k": 0, "j": 2})
+    assert info.K == 0
+    info = analyze("ik", "kj", "ij", {"i": 1, "k": 1, "j": 1})
+    assert (info.M, info.N, info.K) == (1, 1, 1)
+
+
+def test_single_hip_runtime_in_process():
+    """libtc must share PyTorch's HIP runtime: two runtimes in one process do
+    not see the same device."""
+    maps = open("/proc/self/maps").read()
+    libs = set(l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l)
+    assert len(libs) == 1, libs

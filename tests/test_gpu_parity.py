@@ -1,0 +1,159 @@
+"""GPU parity of tc_execute against the CPU oracle, through the C ABI.
+
+Integer-valued inputs make every partial sum exact, so the GPU must agree
+with the oracle bit for bit whatever its summation order; uniform inputs are
+held to a componentwise FP64 bound of 1e-12 of (|A||B|)(c)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_util import FP64_TOL, colmajor_zeros, componentwise_error, reference, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1307_2100_amd as tc  # noqa: E402
+
+RECIPES = ["auto", "gemm", "copy_gemm"]
+
+CASES = [
+    # name, labA, labB, labC, extents (sizes span several tiles plus a ragged tail)
+    ("3d_matrix", "ikm", "kj", "ijm", {"i": 150, "k": 37, "m": 3, "j": 133}),
+    ("cc_a", "abcd", "cdij", "abij", {"a": 12, "b": 11, "c": 9, "d": 7, "i": 6, "j": 5}),
+    ("cc_b", "akic", "kbcj", "abij", {"a": 13, "k": 5, "i": 6, "c": 9, "b": 11, "j": 4}),
+    ("class31", "abg", "gah", "bh", {"a": 33, "b": 70, "g": 17, "h": 129}),
+    ("class32", "abg", "hbg", "ah", {"a": 130, "b": 9, "g": 11, "h": 65}),
+    ("xy_b", "iajb", "jgid", "abgd", {"i": 19, "j": 13, "a": 7, "b": 5, "g": 6, "d": 9}),
+    ("class2", "abg", "bg", "a", {"a": 300, "b": 17, "g": 9}),
+    ("class1", "abg", "abg", "", {"a": 40, "b": 17, "g": 9}),
+    ("outer", "ab", "cd", "acbd", {"a": 20, "b": 7, "c": 31, "d": 3}),
+    ("batch", "acbdx", "cdx", "abx", {"a": 4, "b": 4, "c": 4, "d": 4, "x": 300}),
+    ("c_nonunit_n", "ki", "kj", "ji", {"i": 70, "j": 90, "k": 200}),
+    ("long_k", "ik", "kj", "ij", {"i": 65, "j": 66, "k": 3000}),
+]
+
+
+def _run(labA, labB, labC, A, B, recipe, alpha=1.0, beta=0.0, C0=None, tile_id=-1):
+    dA, dB = to_dev(A), to_dev(B)
+    shape = [dict(zip(labA, A.shape), **dict(zip(labB, B.shape)))[l] for l in labC]
+    C = colmajor_zeros(shape)
+    if C0 is not None:
+        C.copy_(to_dev(C0))
+    plan = tc.Plan.for_tensors(dA, labA, dB, labB, C, labC, recipe=recipe, tile_id=tile_id)
+    plan.execute(dA, dB, C, alpha, beta)
+    torch.cuda.synchronize()
+    info = plan.info.as_dict()
+    plan.close()
+    return C.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("recipe", RECIPES)
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_parity_integer_exact(case, recipe):
+    name, labA, labB, labC, ext = case
+    A, B = synth.make_operands(7, labA, labB, ext, kind="integers")
+    got, info = _run(labA, labB, labC, A, B, recipe)
+    ref = oracle.contract(A, labA, B, labB, labC)
+    print(name, recipe, info["paper_class"], info["recipe_name"], info["M"], info["N"], info["K"], info["L"])
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("recipe", RECIPES)
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_parity_uniform(case, recipe):
+    name, labA, labB, labC, ext = case
+    A, B = synth.make_operands(8, labA, labB, ext, kind="uniform")
+    got, info = _run(labA, labB, labC, A, B, recipe)
+    ref, absr = reference(A, labA, B, labB, labC)
+    err = componentwise_error(got, ref, absr)
+    print(name, recipe, "componentwise error %.3e" % err)
+    assert err <= FP64_TOL
+
+
+@pytest.mark.parametrize("tile_id", [0, 1, 2, 3])
+def test_every_tile_config(tile_id):
+    labA, labB, labC = "akic", "kbcj", "abij"
+    ext = {"a": 37, "k": 5, "i": 6, "c": 9, "b": 29, "j": 4}
+    A, B = synth.make_operands(9, labA, labB, ext, kind="integers")
+    got, info = _run(labA, labB, labC, A, B, "gemm", tile_id=tile_id)
+    assert info["tile_id"] == tile_id
+    assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
+
+
+def test_alpha_beta_and_nan_output():
+    labA, labB, labC, ext = CASES[0][1:]
+    A, B = synth.make_operands(10, labA, labB, ext, kind="integers")
+    shape = [ext[l] for l in labC]
+    C0 = synth.integers(shape, 77)
+    got, _ = _run(labA, labB, labC, A, B, "auto", alpha=-0.5, beta=2.0, C0=C0)
+    assert np.array_equal(got, -0.5 * oracle.contract(A, labA, B, labB, labC) + 2.0 * C0)
+    nan = np.full(shape, np.nan)
+    got, _ = _run(labA, labB, labC, A, B, "auto", alpha=1.0, beta=0.0, C0=nan)
+    assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))   # beta = 0 never reads C
+
+
+def test_strided_views_and_transposed_output():
+    g = np.random.default_rng(5)
+    big = np.asfortranarray(g.integers(-4, 5, size=(60, 50, 9)).astype(np.float64))
+    bigB = np.asfortranarray(g.integers(-4, 5, size=(40, 70)).astype(np.float64))
+    A = big[3:53:2, 1:41, ::2]                               # labels i, k, m (non-contiguous)
+    B = bigB[:, 5:66]
+    dA = to_dev(big)[3:53:2, 1:41, ::2]                      # the same views taken on the device
+    dB = to_dev(bigB)[:, 5:66]
+    assert not dA.is_contiguous() and dA.stride() == tuple(s // 8 for s in A.strides)
+    Ct = torch.zeros(5, 61, 25, dtype=torch.float64, device="cuda").permute(2, 1, 0)   # labels i, j, m
+    Cv = Ct.permute(0, 2, 1)                                # i, m, j view of the same storage
+    plan = tc.Plan.for_tensors(dA, "ikm", dB, "kj", Cv, "imj")
+    plan.execute(dA, dB, Cv)
+    torch.cuda.synchronize()
+    ref = oracle.contract(A, "ikm", B, "kj", "imj")
+    assert np.array_equal(Cv.cpu().numpy(), ref)
+    plan.close()
+
+
+def test_empty_contractions():
+    # empty output: no-op
+    A = np.zeros((0, 5))
+    B = synth.integers((5, 4), 1)
+    got, _ = _run("ik", "kj", "ij", A, B, "auto")
+    assert got.shape == (0, 4)
+    # empty sum: C <- beta * C
+    A = np.zeros((3, 0))
+    B = np.zeros((0, 4))
+    C0 = synth.integers((3, 4), 2)
+    got, _ = _run("ik", "kj", "ij", A, B, "auto", beta=3.0, C0=C0)
+    assert np.array_equal(got, 3.0 * C0)
+    got, _ = _run("ik", "kj", "ij", A, B, "auto", beta=0.0, C0=C0)
+    assert not got.any()
+
+
+def test_random_contractions():
+    g = np.random.default_rng(1307)
+    for t in range(40):
+        la, lb, lc, ext = synth.random_contraction(g, rank_range=(2, 5), ext_range=(2, 12), max_elems=40000,
+                                                   p_outer=0.05, allow_batch=True)
+        A, B = synth.make_operands(100 + t, la, lb, ext, kind="integers")
+        recipe = RECIPES[t % 3]
+        got, info = _run(la, lb, lc, A, B, recipe)
+        ref = oracle.contract(A, la, B, lb, lc)
+        assert np.array_equal(got, ref), (la, lb, lc, ext, recipe, info)
+
+
+def test_permute_entry_point_bit_exact():
+    X = synth.uniform((33, 17, 5, 9), 3)
+    for perm in [(1, 0, 2, 3), (3, 2, 1, 0), (0, 2, 1, 3), (2, 3, 0, 1)]:
+        ext_out = [X.shape[p] for p in perm]
+        st_out = np.cumprod([1] + ext_out[:-1])
+        sY = [0] * 4
+        for pos, p in enumerate(perm):
+            sY[p] = int(st_out[pos])
+        dX = to_dev(X)
+        Y = torch.zeros(X.size, dtype=torch.float64, device="cuda")
+        tc.permute(dX, sY, Y)
+        torch.cuda.synchronize()
+        assert np.array_equal(Y.cpu().numpy(), oracle.permute(X, sY, X.size)), perm
