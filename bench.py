@@ -1,0 +1,214 @@
+"""Benchmark: FP64 contraction throughput on the coupled-cluster workload.
+
+One step = one pass of the hot path over one batch of input: the two
+coupled-cluster contractions at v = 128, o = 32,
+  (a) C[a,b,i,j] = sum_{c,d} A[a,b,c,d] B[c,d,i,j]   (paper class 3.2, direct GEMM)
+  (b) C[a,b,i,j] = sum_{k,c} A[a,k,i,c] B[k,b,c,j]   (class 3.2 with un-fusable index groups)
+each through tc_execute on plans built once.  Inputs are seeded synthetic
+FP64 tensors (uniform in [-1, 1], column-major) resident in HBM before the
+timed region.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--split]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--v", type=int, default=128)
+    ap.add_argument("--o", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU sample")
+    return ap.parse_args()
+
+
+def sha_of(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_src):
+    """HBM traffic of the dominant kernel from committed counter runs, valid
+    only while the kernel source is unchanged since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_gett_f64_cc_a.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha") != sha_of(kernel_src):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1307_2100_amd as tc
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    work = {}
+    for name, spec, wid in (("cc_a", synth.workload_cc_a(args.v, args.o), 1),
+                            ("cc_b", synth.workload_cc_b(args.v, args.o), 2)):
+        labA, labB, labC, ext = spec
+        t0 = time.time()
+        A, B = synth.make_operands(wid, labA, labB, ext, kind="uniform")
+        dA = torch.from_numpy(A).to(dev)
+        dB = torch.from_numpy(B).to(dev)
+        C = tc.empty_colmajor([ext[l] for l in labC], device=dev)
+        C.zero_()
+        tp = time.perf_counter()
+        plan = tc.Plan.for_tensors(dA, labA, dB, labB, C, labC)
+        plan_ms = (time.perf_counter() - tp) * 1e3
+        work[name] = dict(spec=spec, A=A, B=B, dA=dA, dB=dB, C=C, plan=plan, plan_ms=plan_ms,
+                          ws=plan.workspace(dev), gen_s=time.time() - t0)
+        print("[bench] %s ready: %s" % (name, plan.info.as_dict()), file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+
+    def step(evs=None):
+        for name in ("cc_a", "cc_b"):
+            w = work[name]
+            if evs is not None:
+                evs[name][0].record(stream)
+            w["plan"].execute(w["dA"], w["dB"], w["C"], 1.0, 0.0, stream=stream, workspace=w["ws"])
+            if evs is not None:
+                evs[name][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps between two device-wide synchronisations
+    per = {n: [] for n in work}
+    evlist = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        evs = {n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for n in work}
+        step(evs)
+        evlist.append(evs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for evs in evlist:
+        for n in work:
+            per[n].append(evs[n][0].elapsed_time(evs[n][1]))
+
+    flops_step = sum(w["plan"].info.flops for w in work.values())
+    value = flops_step * args.steps / wall / 1e9
+
+    # accuracy on sampled outputs against the compensated oracle (outside the timed region)
+    import oracle
+    errs = {}
+    for name, w in work.items():
+        labA, labB, labC, ext = w["spec"]
+        shape = [ext[l] for l in labC]
+        g = np.random.default_rng(11)
+        idx = np.stack([g.integers(0, e, 512) for e in shape], axis=1)
+        s, a = oracle.contract_entries(w["A"], labA, w["B"], labB, labC, idx)
+        got = w["C"].cpu().numpy()[tuple(idx.T)]
+        errs[name] = float(np.max(np.abs(got - s) / a))
+
+    per_contraction = {}
+    for name, w in work.items():
+        ms = float(np.mean(per[name]))
+        info = w["plan"].info
+        per_contraction[name] = {
+            "ms": round(ms, 4), "tflops": round(info.flops / ms / 1e9, 3),
+            "frac_fp64_peak": round(info.flops / ms / 1e9 / FP64_PEAK_TFLOPS, 4),
+            "paper_class": info.paper_class, "recipe": tc.RECIPE_NAMES[info.recipe], "tile_id": info.tile_id,
+            "M": info.M, "N": info.N, "K": info.K, "plan_create_ms": round(w["plan_ms"], 3),
+            "max_componentwise_error_sampled": errs[name],
+        }
+
+    # dominant kernel: the GEMM launch of contraction (a)
+    ia = work["cc_a"]["plan"].info
+    ms_a = float(np.mean(per["cc_a"]))
+    achieved = ia.flops / (ms_a * 1e-3) / 1e12
+    kernel_src = os.path.join(ROOT, "paper_1307_2100_amd", "csrc", "gett_f64.hip")
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic_from_profile(kernel_src),
+                "kernel": "gett_f64_kernel (contraction a)", "algorithmic_flops_per_launch": ia.flops,
+                "algorithmic_bytes_per_launch": ia.bytes}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(work["cc_a"], args.cpu_seconds)
+
+    out = {
+        "metric": "contraction GFLOP/s (FP64 vs split-BF16) at stated rel. error; % MFMA peak",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded uniform[-1,1], column-major FP64)",
+        "config": {"workload": "coupled-cluster contractions (a) abcd,cdij->abij and (b) akic,kbcj->abij, "
+                               "v=%d o=%d, FP64" % (args.v, args.o),
+                   "v": args.v, "o": args.o, "flops_per_step": flops_step},
+        "frac_fp64_peak": round(value / 1e3 / FP64_PEAK_TFLOPS, 4),
+        "max_componentwise_error": max(errs.values()),
+        "per_contraction": per_contraction,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    for w in work.values():
+        w["plan"].close()
+
+
+def cpu_baseline(w, target_s):
+    """The oracle (plain FP64 nested loop, all host threads it uses) on a
+    bounded sample of contraction (a): whole output entries, each a full
+    K-long sum, timed and scaled to GFLOP/s."""
+    import numpy as np
+
+    import oracle
+    labA, labB, labC, ext = w["spec"]
+    shape = [ext[l] for l in labC]
+    K = w["plan"].info.K
+    g = np.random.default_rng(3)
+    n = 64
+    while True:
+        idx = np.stack([g.integers(0, e, n) for e in shape], axis=1)
+        t0 = time.perf_counter()
+        oracle.contract_entries(w["A"], labA, w["B"], labB, labC, idx, compensated=False, with_abs=False)
+        dt = time.perf_counter() - t0
+        if dt >= target_s * 0.5 or n >= 1 << 22:
+            break
+        n = int(n * min(16.0, max(2.0, target_s / max(dt, 1e-3))))
+    gflops = 2.0 * K * n / dt / 1e9
+    return {"value": round(gflops, 4), "unit": "GFLOP/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": "%d output entries of contraction (a) (each a %d-term sum), %.1f s" % (n, K, dt)}
+
+
+if __name__ == "__main__":
+    main()

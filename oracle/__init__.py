@@ -127,8 +127,8 @@ def contract(A, labA, B, labB, labC, alpha=1.0, beta=0.0, C=None, mode="plain", 
     return C
 
 
-def contract_entries(A, labA, B, labB, labC, cidx, compensated=True, nthreads=0):
-    """Raw sums sum_k A*B and sum_k |A||B| for selected output entries.
+def contract_entries(A, labA, B, labB, labC, cidx, compensated=True, nthreads=0, with_abs=True):
+    """Raw sums sum_k A*B and (with_abs) sum_k |A||B| for selected output entries.
 
     cidx: (n, rank C) integer array of output multi-indices in labC order."""
     lib = _load()
@@ -143,7 +143,8 @@ def contract_entries(A, labA, B, labB, labC, cidx, compensated=True, nthreads=0)
     da, db = _desc(A, labA), _desc(B, labB)
     rc = lib.tco_contract_entries(*da, *db, len(lc), _i64(extC), _i32(lc), _dptr(A), _dptr(B), n,
                                   cidx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                  _dptr(s), _dptr(a), 1 if compensated else 0, int(nthreads))
+                                  _dptr(s), _dptr(a) if with_abs else None, 1 if compensated else 0,
+                                  int(nthreads))
     if rc:
         raise ValueError("oracle rejected the contraction (code %d)" % rc)
     return s, a

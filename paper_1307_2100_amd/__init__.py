@@ -42,6 +42,8 @@ PRECISIONS = {"f64": 0, "split_bf16": 1, "split_fp8": 2}
 TC_RECIPE_AUTO, TC_RECIPE_GEMM, TC_RECIPE_COPY_GEMM, TC_RECIPE_GEMV, TC_RECIPE_GER, TC_RECIPE_DOT = range(6)
 RECIPES = {"auto": 0, "gemm": 1, "copy_gemm": 2, "gemv": 3, "ger": 4, "dot": 5}
 RECIPE_NAMES = {v: k for k, v in RECIPES.items()}
+# GEMM tile configurations compiled into libtc (ids 0 .. NUM_TILES-1)
+NUM_TILES = 14
 # tc_picker
 TC_PICKER_RULES, TC_PICKER_MLP, TC_PICKER_TUNED = 0, 1, 2
 

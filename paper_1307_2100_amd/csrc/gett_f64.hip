@@ -22,23 +22,24 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;
-
 // LDS layout of one staged operand tile with R rows and BK contracted
 // indices: k-contiguous when the operand is k-fast, row-contiguous otherwise.
+// The k-contiguous rows are padded to an even length so that a lane can read
+// four consecutive k values with two 16-byte LDS reads.
 template <int R, int BK, bool KF>
 struct Stage {
-  static constexpr int LD = KF ? (BK + 1) : (R + 4);
+  static constexpr int LD = KF ? (BK + 2) : (R + 4);
   static constexpr int SIZE = KF ? R * LD : BK * LD;
   __device__ static inline int at(int k, int r) { return KF ? r * LD + k : k * LD + r; }
 };
 
-// Global-to-register loader for one operand tile (R rows x BK contracted).
-template <int R, int BK, bool KF>
+// Global-to-register loader for one operand tile (R rows x BK contracted)
+// with NT threads.
+template <int R, int BK, bool KF, int NT>
 struct Loader {
-  static constexpr int E = R * BK / kThreads;  // elements per thread
-  static_assert(kThreads % R == 0 || KF, "row-fast loader needs R | 256");
-  static_assert(kThreads % BK == 0, "BK | 256");
+  static constexpr int E = R * BK / NT;  // elements per thread
+  static_assert(E >= 1 && R * BK == E * NT, "tile must split evenly over the threads");
+  static_assert(KF ? (NT % BK == 0) : (NT % R == 0), "loader mapping needs whole rows per pass");
   int64_t roff[KF ? E : 1];  // row offsets (row-fast: one row per thread)
   double v[E];
 
@@ -46,7 +47,7 @@ struct Loader {
     if constexpr (KF) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        int64_t r = r0 + tid / BK + (kThreads / BK) * e;
+        int64_t r = r0 + tid / BK + (NT / BK) * e;
         roff[e] = r < rows ? off_at(xr, r) : -1;
       }
     } else {
@@ -62,11 +63,11 @@ struct Loader {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = (ko >= 0 && roff[e] >= 0) ? X[roff[e] + ko] : 0.0;
     } else {
-      // every lane of a wavefront shares the same k: keep it scalar
-      const int kf = __builtin_amdgcn_readfirstlane(tid / R);
+      // all lanes of a wavefront share one k when R is a multiple of 64: keep it scalar
+      const int kf = R % 64 == 0 ? __builtin_amdgcn_readfirstlane(tid / R) : tid / R;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        int64_t k = k0 + kf + (kThreads / R) * e;
+        int64_t k = k0 + kf + (NT / R) * e;
         int64_t ko = k < K ? off_at(xk, k) : -1;
         v[e] = (ko >= 0 && roff[0] >= 0) ? X[roff[0] + ko] : 0.0;
       }
@@ -78,9 +79,42 @@ struct Loader {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       if constexpr (KF) {
-        s[S::at(tid % BK, tid / BK + (kThreads / BK) * e)] = v[e];
+        s[S::at(tid % BK, tid / BK + (NT / BK) * e)] = v[e];
       } else {
-        s[S::at(tid / R + (kThreads / R) * e, tid % R)] = v[e];
+        s[S::at(tid / R + (NT / R) * e, tid % R)] = v[e];
+      }
+    }
+  }
+};
+
+// Fragment reads for one 4-deep MFMA step.  Inside a BK tile the lanes of
+// quarter q (lane / 16) take contracted indices 4q .. 4q+3 of each 16-wide
+// chunk, step s using index 4q + s: any bijection of k inside the tile gives
+// the same sum, and this one makes a lane's four values adjacent in a
+// k-contiguous stage.
+template <int R, int BK, bool KF, int T>
+struct Frags {
+  double f[BK / 4][T];
+  __device__ inline void read(const double* __restrict__ s, int row0, int fr, int fk) {
+    using S = Stage<R, BK, KF>;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+      for (int c = 0; c < BK / 16; ++c) {
+        const int r = row0 + t * 16 + fr;
+        const int kb = c * 16 + fk * 4;
+        if constexpr (KF) {
+          typedef double d2 __attribute__((ext_vector_type(2)));
+          const d2 lo = *reinterpret_cast<const d2*>(s + S::at(kb, r));
+          const d2 hi = *reinterpret_cast<const d2*>(s + S::at(kb + 2, r));
+          f[c * 4 + 0][t] = lo.x;
+          f[c * 4 + 1][t] = lo.y;
+          f[c * 4 + 2][t] = hi.x;
+          f[c * 4 + 3][t] = hi.y;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) f[c * 4 + q][t] = s[S::at(kb + q, r)];
+        }
       }
     }
   }
@@ -107,21 +141,23 @@ __device__ inline void tile_of(int64_t bid, int64_t total, int64_t tilesM, int64
   *tn = w / gs;
 }
 
-template <int BM, int BN, int BK, bool AKF, bool BKF>
-__global__ __launch_bounds__(kThreads) void gett_f64_kernel(GettParams p, int64_t tilesM, int64_t tilesN,
-                                                             int64_t total) {
+template <int BM, int BN, int BK, int WGM, int WGN, bool AKF, bool BKF>
+__global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_kernel(GettParams p, int64_t tilesM, int64_t tilesN,
+                                                                   int64_t total) {
+  constexpr int NT = 64 * WGM * WGN;
   using SA_ = Stage<BM, BK, AKF>;
   using SB_ = Stage<BN, BK, BKF>;
-  __shared__ double sA[2][SA_::SIZE];
-  __shared__ double sB[2][SB_::SIZE];
+  __shared__ __attribute__((aligned(16))) double sA[2][SA_::SIZE];
+  __shared__ __attribute__((aligned(16))) double sB[2][SB_::SIZE];
 
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int TM = WM / 16, TN = WN / 16;
+  static_assert(BK % 16 == 0 && TM >= 1 && TN >= 1, "tile shape");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WGM, wn = wave / WGM;
 
   int64_t l, tm, tn;
   tile_of(blockIdx.x, total, tilesM, tilesN, &l, &tm, &tn);
@@ -130,8 +166,8 @@ __global__ __launch_bounds__(kThreads) void gett_f64_kernel(GettParams p, int64_
   const double* __restrict__ A = p.A + off_at(p.aL, l);
   const double* __restrict__ B = p.B + off_at(p.bL, l);
 
-  Loader<BM, BK, AKF> la;
-  Loader<BN, BK, BKF> lb;
+  Loader<BM, BK, AKF, NT> la;
+  Loader<BN, BK, BKF, NT> lb;
   la.init(p.aM, m0, p.M, tid);
   lb.init(p.bN, n0, p.N, tid);
 
@@ -151,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void gett_f64_kernel(GettParams p, int64_
   __syncthreads();
 
   const int fr = lane & 15;   // row (A) / column (B) inside a 16x16 block
-  const int fk = lane >> 4;   // contracted index inside a 4-deep step
+  const int fk = lane >> 4;   // lane quarter: which 4 contracted indices of a 16-chunk
   for (int64_t kt = 0; kt < ktiles; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < ktiles;
@@ -159,20 +195,17 @@ __global__ __launch_bounds__(kThreads) void gett_f64_kernel(GettParams p, int64_
       la.load(A, p.aK, (kt + 1) * BK, p.K, tid);
       lb.load(B, p.bK, (kt + 1) * BK, p.K, tid);
     }
-    const double* a_s = sA[cur];
-    const double* b_s = sB[cur];
+    Frags<BM, BK, AKF, TM> fa;
+    Frags<BN, BK, BKF, TN> fb;
+    fa.read(sA[cur], wm * WM, fr, fk);
+    fb.read(sB[cur], wn * WN, fr, fk);
 #pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      double af[TM], bf[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) af[i] = a_s[SA_::at(kk * 4 + fk, wm * WM + i * 16 + fr)];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) bf[j] = b_s[SB_::at(kk * 4 + fk, wn * WN + j * 16 + fr)];
+    for (int s = 0; s < BK / 4; ++s)
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.f[s][i], fb.f[s][j], acc[i][j], 0, 0, 0);
     if (more) {
       la.store(sA[cur ^ 1], tid);
       lb.store(sB[cur ^ 1], tid);
@@ -208,21 +241,25 @@ __global__ __launch_bounds__(kThreads) void gett_f64_kernel(GettParams p, int64_
   }
 }
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, int WGM, int WGN>
 hipError_t launch_cfg(const GettParams& p, bool akf, bool bkf, hipStream_t s) {
   const int64_t tilesM = (p.M + BM - 1) / BM, tilesN = (p.N + BN - 1) / BN;
   const int64_t total = tilesM * tilesN * p.L;
   if (total == 0) return hipSuccess;
   if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  dim3 grid((unsigned)total), block(kThreads);
+  dim3 grid((unsigned)total), block(64 * WGM * WGN);
   if (akf && bkf)
-    hipLaunchKernelGGL((gett_f64_kernel<BM, BN, BK, true, true>), grid, block, 0, s, p, tilesM, tilesN, total);
+    hipLaunchKernelGGL((gett_f64_kernel<BM, BN, BK, WGM, WGN, true, true>), grid, block, 0, s, p, tilesM, tilesN,
+                       total);
   else if (akf)
-    hipLaunchKernelGGL((gett_f64_kernel<BM, BN, BK, true, false>), grid, block, 0, s, p, tilesM, tilesN, total);
+    hipLaunchKernelGGL((gett_f64_kernel<BM, BN, BK, WGM, WGN, true, false>), grid, block, 0, s, p, tilesM, tilesN,
+                       total);
   else if (bkf)
-    hipLaunchKernelGGL((gett_f64_kernel<BM, BN, BK, false, true>), grid, block, 0, s, p, tilesM, tilesN, total);
+    hipLaunchKernelGGL((gett_f64_kernel<BM, BN, BK, WGM, WGN, false, true>), grid, block, 0, s, p, tilesM, tilesN,
+                       total);
   else
-    hipLaunchKernelGGL((gett_f64_kernel<BM, BN, BK, false, false>), grid, block, 0, s, p, tilesM, tilesN, total);
+    hipLaunchKernelGGL((gett_f64_kernel<BM, BN, BK, WGM, WGN, false, false>), grid, block, 0, s, p, tilesM,
+                       tilesN, total);
   return hipGetLastError();
 }
 
@@ -230,10 +267,10 @@ hipError_t launch_cfg(const GettParams& p, bool akf, bool bkf, hipStream_t s) {
 
 hipError_t launch_gett_f64(const GettParams& p, int tile_id, bool a_kfast, bool b_kfast, hipStream_t s) {
   switch (tile_id) {
-    case 0: return launch_cfg<128, 128, 16>(p, a_kfast, b_kfast, s);
-    case 1: return launch_cfg<64, 64, 16>(p, a_kfast, b_kfast, s);
-    case 2: return launch_cfg<128, 64, 16>(p, a_kfast, b_kfast, s);
-    case 3: return launch_cfg<64, 128, 16>(p, a_kfast, b_kfast, s);
+#define TC_TILE(id, bm, bn, bk, wgm, wgn) \
+  case id: return launch_cfg<bm, bn, bk, wgm, wgn>(p, a_kfast, b_kfast, s);
+    TC_GETT_TILES(TC_TILE)
+#undef TC_TILE
     default: return hipErrorInvalidValue;
   }
 }

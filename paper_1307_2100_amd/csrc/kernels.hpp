@@ -30,12 +30,30 @@ struct GettParams {
   double alpha, beta;
 };
 
-// Tile configurations of the GEMM kernel (rows x columns x contracted).
+// Tile configurations of the GEMM kernel: (id, rows, columns, contracted
+// depth, wavefronts along rows, wavefronts along columns).
+#define TC_GETT_TILES(X)      \
+  X(0, 128, 128, 16, 2, 2)    \
+  X(1, 64, 64, 16, 2, 2)      \
+  X(2, 128, 64, 16, 2, 2)     \
+  X(3, 64, 128, 16, 2, 2)     \
+  X(4, 64, 64, 32, 2, 2)      \
+  X(5, 128, 128, 16, 2, 4)    \
+  X(6, 128, 64, 32, 2, 2)     \
+  X(7, 64, 128, 32, 2, 2)     \
+  X(8, 32, 32, 16, 2, 2)      \
+  X(9, 128, 128, 32, 4, 4)    \
+  X(10, 128, 128, 16, 4, 4)   \
+  X(11, 256, 128, 16, 4, 4)   \
+  X(12, 128, 256, 16, 4, 4)   \
+  X(13, 128, 128, 32, 2, 4)
 struct TileCfg {
-  int bm, bn, bk;
+  int id, bm, bn, bk, wgm, wgn;
 };
-constexpr TileCfg kTiles[4] = {{128, 128, 16}, {64, 64, 16}, {128, 64, 16}, {64, 128, 16}};
-constexpr int kNumTiles = 4;
+#define TC_TILE_ENTRY(id, bm, bn, bk, wgm, wgn) {id, bm, bn, bk, wgm, wgn},
+constexpr TileCfg kTiles[] = {TC_GETT_TILES(TC_TILE_ENTRY)};
+#undef TC_TILE_ENTRY
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 hipError_t launch_gett_f64(const GettParams& p, int tile_id, bool a_kfast, bool b_kfast, hipStream_t s);
 

@@ -14,6 +14,8 @@
 // (an outer product) is reported as class 0.
 #include "planner.hpp"
 
+#include "kernels.hpp"
+
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -124,14 +126,16 @@ int64_t product(const TensorDesc& t) {
   return p;
 }
 
-// Rule picker for the GEMM tile: the largest tile that still gives the chip
-// (256 compute units) a few workgroups each.
+// Rule picker for the GEMM tile: the largest tile (most wavefronts per
+// workgroup, most reuse per byte staged) that still gives each of the 256
+// compute units a workgroup; smaller tiles as the problem shrinks.
 int pick_tile(int64_t M, int64_t N, int64_t L) {
   auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * L; };
-  if (tiles(128, 128) >= 512) return 0;
-  if (M >= N && tiles(128, 64) >= 512) return 2;
-  if (N > M && tiles(64, 128) >= 512) return 3;
-  return 1;
+  if (tiles(256, 128) >= 256) return 11;
+  if (tiles(128, 256) >= 256) return 12;
+  if (tiles(128, 128) >= 256) return 9;
+  if (tiles(64, 64) >= 256) return 1;
+  return 8;
 }
 
 }  // namespace
@@ -189,7 +193,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     }
   }
   if (opt.precision < TC_PREC_F64 || opt.precision > TC_PREC_F64_SPLIT_FP8 || opt.recipe < TC_RECIPE_AUTO ||
-      opt.recipe > TC_RECIPE_DOT || opt.tile_id < -1 || opt.tile_id > 3 || opt.split_slices < 0 ||
+      opt.recipe > TC_RECIPE_DOT || opt.tile_id < -1 || opt.tile_id >= kNumTiles || opt.split_slices < 0 ||
       opt.split_slices > 8) {
     *err = "invalid tc_options field";
     return TC_ERR_INVALID_ARG;

@@ -75,7 +75,7 @@ def test_parity_uniform(case, recipe):
     assert err <= FP64_TOL
 
 
-@pytest.mark.parametrize("tile_id", [0, 1, 2, 3])
+@pytest.mark.parametrize("tile_id", list(range(tc.NUM_TILES)))
 def test_every_tile_config(tile_id):
     labA, labB, labC = "akic", "kbcj", "abij"
     ext = {"a": 37, "k": 5, "i": 6, "c": 9, "b": 29, "j": 4}
