@@ -223,6 +223,15 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
   gp.L = info.L;
   gp.alpha = alpha;
   gp.beta = beta;
+  if (an.kernel == tc::Analysis::KERNEL_LANES_OUT) {
+    e = tc::launch_lanes_over_outputs(gp, an.n_fastest, s);
+    return e == hipSuccess ? TC_OK : hip_fail(e, "lanes-over-outputs launch");
+  }
+  if (an.kernel == tc::Analysis::KERNEL_LANES_K) {
+    double* part = an.seg > 1 ? (double*)((char*)workspace + an.part_offset) : nullptr;
+    e = tc::launch_lanes_over_k(gp, an.seg, part, s);
+    return e == hipSuccess ? TC_OK : hip_fail(e, "lanes-over-k launch");
+  }
   int tile = info.tile_id >= 0 ? info.tile_id : 1;
   e = tc::launch_gett_f64(gp, tile, an.a_kfast, an.b_kfast, s);
   if (e != hipSuccess) return hip_fail(e, "gett launch");

@@ -1,0 +1,150 @@
+// Matrix-vector, inner-product and outer-product recipes (paper Sec. 2.2 and
+// Sec. 3.2: Class 2 -> GEMV, Class 1 -> DOT, all contracted indices sliced ->
+// a sum of GERs).  These contractions move many bytes per flop, so the
+// kernels are built around coalescing rather than matrix cores:
+//
+//  * outputs-along-lanes (GEMV-N, fused GER sum): one thread owns one output
+//    entry and walks the contracted index; consecutive lanes own consecutive
+//    entries along the index that is stride-1 in memory, so each step of the
+//    walk is one coalesced row of the matrix operand.  Summing the rank-1
+//    updates in registers writes C once instead of once per update.
+//  * k-along-lanes (GEMV-T, DOT): a wavefront owns one output entry (or one
+//    segment of its contracted range); lanes stride along the contracted
+//    stride-1 index and combine with a cross-lane reduction.  When few
+//    outputs exist, the contracted range is cut into segments whose partial
+//    sums go to the workspace and a second pass adds them in a fixed order
+//    (deterministic).
+#include "kernels.hpp"
+
+namespace tc {
+namespace {
+
+__global__ __launch_bounds__(256) void lanes_over_outputs_kernel(GettParams p, int n_fastest, int64_t total) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= total) return;
+  int64_t m, n, l;
+  if (n_fastest) {
+    n = o % p.N;
+    const int64_t r = o / p.N;
+    m = r % p.M;
+    l = r / p.M;
+  } else {
+    m = o % p.M;
+    const int64_t r = o / p.M;
+    n = r % p.N;
+    l = r / p.N;
+  }
+  const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
+  const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  int64_t k = 0;
+  for (; k + 4 <= p.K; k += 4) {
+    acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
+    acc1 += A[off_at(p.aK, k + 1)] * B[off_at(p.bK, k + 1)];
+    acc2 += A[off_at(p.aK, k + 2)] * B[off_at(p.bK, k + 2)];
+    acc3 += A[off_at(p.aK, k + 3)] * B[off_at(p.bK, k + 3)];
+  }
+  for (; k < p.K; ++k) acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
+  const double s = (acc0 + acc1) + (acc2 + acc3);
+  double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
+  *dst = p.beta == 0.0 ? p.alpha * s : p.alpha * s + p.beta * *dst;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One wavefront per (output entry, contracted segment).  seg == 1 writes C;
+// otherwise the partial sum goes to part[o * seg + s].
+__global__ __launch_bounds__(256) void lanes_over_k_kernel(GettParams p, int64_t outputs, int64_t seg,
+                                                           int64_t seg_len, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (w >= outputs * seg) return;
+  const int64_t o = w / seg, s = w % seg;
+  const int64_t m = o % p.M;
+  const int64_t r = o / p.M;
+  const int64_t n = r % p.N;
+  const int64_t l = r / p.N;
+  const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
+  const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
+  const int64_t k0 = s * seg_len;
+  const int64_t k1 = k0 + seg_len < p.K ? k0 + seg_len : p.K;
+  double acc0 = 0.0, acc1 = 0.0;
+  int64_t k = k0 + lane;
+  for (; k + 64 < k1; k += 128) {
+    acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
+    acc1 += A[off_at(p.aK, k + 64)] * B[off_at(p.bK, k + 64)];
+  }
+  if (k < k1) acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
+  const double v = wave_sum(acc0 + acc1);
+  if (lane != 0) return;
+  if (seg == 1) {
+    double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
+    *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
+  } else {
+    part[o * seg + s] = v;
+  }
+}
+
+// Second pass: output o adds its seg partial sums in segment order.
+__global__ __launch_bounds__(256) void sum_partials_kernel(GettParams p, int64_t outputs, int64_t seg,
+                                                           const double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int64_t o = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (o >= outputs) return;
+  // lanes take segments lane, lane+64, ...; the reduction tree is fixed
+  double acc = 0.0;
+  for (int64_t s = lane; s < seg; s += 64) acc += part[o * seg + s];
+  const double v = wave_sum(acc);
+  if (lane != 0) return;
+  const int64_t m = o % p.M;
+  const int64_t r = o / p.M;
+  const int64_t n = r % p.N;
+  const int64_t l = r / p.N;
+  double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
+  *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
+}
+
+}  // namespace
+
+hipError_t launch_lanes_over_outputs(const GettParams& p, bool n_fastest, hipStream_t s) {
+  const int64_t total = p.M * p.N * p.L;
+  if (total == 0) return hipSuccess;
+  const int64_t blocks = (total + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(lanes_over_outputs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n_fastest ? 1 : 0,
+                     total);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanes_over_k(const GettParams& p, int64_t seg, double* part, hipStream_t s) {
+  const int64_t outputs = p.M * p.N * p.L;
+  if (outputs == 0) return hipSuccess;
+  if (seg < 1) seg = 1;
+  const int64_t seg_len = (p.K + seg - 1) / seg;
+  const int64_t waves = outputs * seg;
+  const int64_t blocks = (waves + 3) / 4;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(lanes_over_k_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, outputs, seg, seg_len, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || seg == 1) return e;
+  const int64_t rblocks = (outputs + 3) / 4;
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)rblocks), dim3(256), 0, s, p, outputs, seg, part);
+  return hipGetLastError();
+}
+
+int64_t k_segments(int64_t outputs, int64_t K) {
+  // Enough wavefronts to cover the chip (about 8 per SIMD), but segments of at
+  // least 4096 contracted indices so that the second pass stays negligible.
+  const int64_t target_waves = 256 * 4 * 8;
+  if (outputs >= target_waves || K <= 8192) return 1;
+  int64_t seg = (target_waves + outputs - 1) / outputs;
+  const int64_t max_seg = K / 4096;
+  if (seg > max_seg) seg = max_seg;
+  return seg < 1 ? 1 : seg;
+}
+
+}  // namespace tc

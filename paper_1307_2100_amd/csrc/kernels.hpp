@@ -57,6 +57,15 @@ constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 hipError_t launch_gett_f64(const GettParams& p, int tile_id, bool a_kfast, bool b_kfast, hipStream_t s);
 
+// GEMV / GER family: one thread per output entry walking the contracted
+// index (consecutive lanes along n when n_fastest, else along m).
+hipError_t launch_lanes_over_outputs(const GettParams& p, bool n_fastest, hipStream_t s);
+// GEMV-T / DOT family: one wavefront per (output entry, contracted segment);
+// seg > 1 needs part[] of M*N*L*seg doubles and adds a second pass.
+hipError_t launch_lanes_over_k(const GettParams& p, int64_t seg, double* part, hipStream_t s);
+// Number of contracted segments the DOT family uses for this many outputs.
+int64_t k_segments(int64_t outputs, int64_t K);
+
 // Y[sum idx_i sy_i] = X[sum idx_i sx_i] over all multi-indices.
 struct PermuteParams {
   const double* X;

@@ -320,6 +320,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     bool a_unit = unit_in(G[GK], SA) && an.copy_slot != SA;
     bool b_unit = unit_in(G[GK], SB) && an.copy_slot != SB;
     if (!a_unit && b_unit) key = SB;
+    if (a_unit && b_unit && an.elems[SB] > an.elems[SA]) key = SB;  // the larger operand reads contiguously
     if (an.copy_slot == SA) key = SB;
     order_group(G[GK], key, key == SA ? SB : SA);
   }
@@ -374,8 +375,37 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
   info.nL = G[GL].n;
   info.flops = 2.0 * (double)info.M * (double)info.N * (double)info.K * (double)info.L;
   info.bytes = 8.0 * ((double)product(A0) + (double)product(B0) + (double)product(C0));
-  if (recipe == TC_RECIPE_GEMM || recipe == TC_RECIPE_COPY_GEMM)
+  if (recipe == TC_RECIPE_GEMM || recipe == TC_RECIPE_COPY_GEMM) {
     info.tile_id = opt.tile_id >= 0 ? opt.tile_id : pick_tile(info.M, info.N, info.L);
+  } else {
+    // Memory-bound recipes (Sec. 3.2, Classes 1 and 2, and the GER slicing).
+    // GER sums its rank-1 updates in registers, one thread per output entry.
+    // GEMV walks the matrix along whichever index is stride-1: its free index
+    // (one thread per output) or its contracted index (lanes along k, with a
+    // cross-lane sum).  DOT always puts the lanes along k.
+    bool c_nfast = G[GN].n > 0 && G[GN].str[SC][0] == 1;
+    an.n_fastest = b_nfast || (c_nfast && !a_mfast);
+    const int64_t outputs = info.M * info.N * info.L;
+    bool lanes_k;
+    if (recipe == TC_RECIPE_GER) {
+      lanes_k = false;
+    } else if (recipe == TC_RECIPE_DOT) {
+      lanes_k = true;
+    } else {
+      // the matrix operand is the one with more entries
+      const bool a_is_matrix = an.elems[SA] >= an.elems[SB];
+      const bool matrix_kfast = a_is_matrix ? an.a_kfast : an.b_kfast;
+      lanes_k = matrix_kfast || (outputs < 4096 && info.K > 4096);
+    }
+    an.kernel = lanes_k ? Analysis::KERNEL_LANES_K : Analysis::KERNEL_LANES_OUT;
+    if (lanes_k && !an.empty_out && !an.empty_sum) {
+      an.seg = k_segments(outputs, info.K);
+      if (an.seg > 1) {
+        an.part_offset = (info.workspace_bytes + 255) / 256 * 256;
+        info.workspace_bytes = an.part_offset + (size_t)(outputs * an.seg) * sizeof(double);
+      }
+    }
+  }
   *out = an;
   return TC_OK;
 }

@@ -57,6 +57,12 @@ struct Analysis {
   bool empty_sum = false;   // some contracted extent is 0: C <- beta * C
   bool a_kfast = false;     // kernel A's stride-1 mode leads the contracted group
   bool b_kfast = false;     // kernel B's stride-1 mode leads the contracted group
+  // GEMV / DOT / GER recipes: which memory-bound kernel runs them
+  enum { KERNEL_GETT = 0, KERNEL_LANES_OUT = 1, KERNEL_LANES_K = 2 };
+  int kernel = KERNEL_GETT;
+  bool n_fastest = false;   // lanes-over-outputs: consecutive lanes along n
+  int64_t seg = 1;          // lanes-over-k: contracted segments per output
+  size_t part_offset = 0;   // byte offset of the partial sums in the workspace
   int64_t elems[3] = {};    // entries of kernel A, kernel B, C (products of extents)
   // COPY_GEMM: the copied operand (kernel slot) and its modes before and after
   // the copy, in the copied tensor's own storage order.

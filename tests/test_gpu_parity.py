@@ -19,7 +19,7 @@ if not torch.cuda.is_available():
 
 import paper_1307_2100_amd as tc  # noqa: E402
 
-RECIPES = ["auto", "gemm", "copy_gemm"]
+RECIPES = ["auto", "gemm", "copy_gemm", "gemv", "ger", "dot"]
 
 CASES = [
     # name, labA, labB, labC, extents (sizes span several tiles plus a ragged tail)
@@ -138,7 +138,7 @@ def test_random_contractions():
         la, lb, lc, ext = synth.random_contraction(g, rank_range=(2, 5), ext_range=(2, 12), max_elems=40000,
                                                    p_outer=0.05, allow_batch=True)
         A, B = synth.make_operands(100 + t, la, lb, ext, kind="integers")
-        recipe = RECIPES[t % 3]
+        recipe = RECIPES[t % len(RECIPES)]
         got, info = _run(la, lb, lc, A, B, recipe)
         ref = oracle.contract(A, la, B, lb, lc)
         assert np.array_equal(got, ref), (la, lb, lc, ext, recipe, info)
@@ -157,3 +157,23 @@ def test_permute_entry_point_bit_exact():
         tc.permute(dX, sY, Y)
         torch.cuda.synchronize()
         assert np.array_equal(Y.cpu().numpy(), oracle.permute(X, sY, X.size)), perm
+
+
+@pytest.mark.parametrize("case", [
+    # class 1 with a long sum: the DOT recipe splits k into segments (second pass)
+    ("dot_long", "abc", "abc", "", {"a": 64, "b": 128, "c": 96}),
+    # class 2, matrix stride-1 index free (lanes over outputs) and contracted (lanes over k)
+    ("gemv_n", "abg", "bg", "a", {"a": 5000, "b": 33, "g": 7}),
+    ("gemv_t", "bga", "bg", "a", {"a": 300, "b": 129, "g": 40}),
+    ("gemv_few_outputs", "abg", "bg", "a", {"a": 3, "b": 2000, "g": 9}),
+])
+def test_memory_bound_recipes(case):
+    name, labA, labB, labC, ext = case
+    A, B = synth.make_operands(12, labA, labB, ext, kind="integers")
+    got, info = _run(labA, labB, labC, A, B, "auto")
+    print(name, info)
+    assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
+    A, B = synth.make_operands(13, labA, labB, ext, kind="uniform")
+    got, info = _run(labA, labB, labC, A, B, "auto", alpha=0.5)
+    ref, absr = reference(A, labA, B, labB, labC, alpha=0.5)
+    assert componentwise_error(got, ref, absr) <= FP64_TOL
