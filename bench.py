@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--o", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU sample")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-precision runs")
+    ap.add_argument("--precision-workload", action="store_true",
+                    help="also run the precision workload (v=192, o=48, N(0,1)*10^U(-3,3) inputs)")
     return ap.parse_args()
 
 
@@ -158,6 +161,19 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(work["cc_a"], args.cpu_seconds)
 
+    split = None
+    if not args.no_split:
+        split = split_runs(work, max(3, min(args.steps, 10)))
+
+    precision_workload = None
+    if args.precision_workload:
+        for w in work.values():
+            w["plan"].close()
+            for key in ("dA", "dB", "C", "ws"):
+                w[key] = None
+        torch.cuda.empty_cache()
+        precision_workload = precision_runs(args)
+
     out = {
         "metric": "contraction GFLOP/s (FP64 vs split-BF16) at stated rel. error; % MFMA peak",
         "value": round(value, 2),
@@ -177,12 +193,105 @@ def main():
         "frac_fp64_peak": round(value / 1e3 / FP64_PEAK_TFLOPS, 4),
         "max_componentwise_error": max(errs.values()),
         "per_contraction": per_contraction,
+        "split_precision": split,
+        "precision_workload": precision_workload,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     for w in work.values():
         w["plan"].close()
+
+
+def sampled_error(A, labA, B, labB, labC, ext, C_dev, n=512, seed=11):
+    """Max componentwise error of C_dev against the compensated oracle on n
+    sampled output entries (each computed in full by the oracle)."""
+    import numpy as np
+
+    import oracle
+    shape = [ext[l] for l in labC]
+    g = np.random.default_rng(seed)
+    idx = np.stack([g.integers(0, e, n) for e in shape], axis=1)
+    s, a = oracle.contract_entries(A, labA, B, labB, labC, idx)
+    got = C_dev.cpu().numpy()[tuple(idx.T)]
+    return float(np.max(np.abs(got - s) / a))
+
+
+def time_plan(plan, dA, dB, C, reps, stream):
+    import numpy as np
+    import torch
+    ws = plan.workspace(C.device)
+    plan.execute(dA, dB, C, 1.0, 0.0, stream=stream, workspace=ws)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.execute(dA, dB, C, 1.0, 0.0, stream=stream, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return float(np.mean(ms))
+
+
+def split_runs(work, reps):
+    """Split-precision (BF16 and FP8 digits) on the same inputs: time (HIP
+    events around each tc_execute, split pass included) and sampled error."""
+    import torch
+
+    import paper_1307_2100_amd as tc
+    stream = torch.cuda.current_stream()
+    out = {}
+    for prec in ("split_bf16", "split_fp8"):
+        res = {}
+        for name, w in work.items():
+            labA, labB, labC, ext = w["spec"]
+            C = tc.empty_colmajor([ext[l] for l in labC], device=w["C"].device)
+            plan = tc.Plan.for_tensors(w["dA"], labA, w["dB"], labB, C, labC, precision=prec)
+            ms = time_plan(plan, w["dA"], w["dB"], C, reps, stream)
+            err = sampled_error(w["A"], labA, w["B"], labB, labC, ext, C)
+            res[name] = {"ms": round(ms, 4), "effective_tflops": round(plan.info.flops / ms / 1e9, 3),
+                         "digits": plan.info.split_slices, "max_componentwise_error_sampled": err,
+                         "workspace_gb": round(plan.info.workspace_bytes / 1e9, 3)}
+            plan.close()
+            del C
+        out[prec] = res
+    return out
+
+
+def precision_runs(args):
+    """The precision workload: both coupled-cluster contractions at v=192,
+    o=48 with N(0,1) inputs scaled per last-index slice by 10^U(-3,3), in FP64,
+    split BF16 and split FP8, each with its sampled error against the oracle."""
+    import torch
+
+    import paper_1307_2100_amd as tc
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, spec, wid in (("cc_a", synth.workload_cc_a(192, 48), 21), ("cc_b", synth.workload_cc_b(192, 48), 22)):
+        labA, labB, labC, ext = spec
+        A, B = synth.make_operands(wid, labA, labB, ext, kind="scaled_normal")
+        dA = torch.from_numpy(A).to(dev)
+        dB = torch.from_numpy(B).to(dev)
+        C = tc.empty_colmajor([ext[l] for l in labC], device=dev)
+        res = {}
+        for prec in ("f64", "split_bf16", "split_fp8"):
+            plan = tc.Plan.for_tensors(dA, labA, dB, labB, C, labC, precision=prec)
+            ms = time_plan(plan, dA, dB, C, 3, stream)
+            err = sampled_error(A, labA, B, labB, labC, ext, C, n=256)
+            res[prec] = {"ms": round(ms, 3), "effective_tflops": round(plan.info.flops / ms / 1e9, 3),
+                         "max_componentwise_error_sampled": err,
+                         "digits": plan.info.split_slices if prec != "f64" else None}
+            plan.close()
+            torch.cuda.empty_cache()
+        res["speedup_split_bf16_vs_f64"] = round(res["f64"]["ms"] / res["split_bf16"]["ms"], 3)
+        out[name] = res
+        print("[bench] precision workload %s: %s" % (name, res), file=sys.stderr, flush=True)
+        del dA, dB, C
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(w, target_s):

@@ -172,7 +172,6 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
   if (workspace_bytes < info.workspace_bytes || (info.workspace_bytes && !workspace))
     return fail(TC_ERR_WORKSPACE, "workspace of " + std::to_string(workspace_bytes) + " bytes, plan needs " +
                                       std::to_string(info.workspace_bytes));
-  if (info.precision != TC_PREC_F64) return fail(TC_ERR_UNSUPPORTED, "split precision is not built in");
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -185,6 +184,41 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
   }
   const double* KA = info.swapped ? B : A;
   const double* KB = info.swapped ? A : B;
+
+  if (info.precision != TC_PREC_F64) {
+    tc::SplitParams sp{};
+    sp.A = KA;
+    sp.B = KB;
+    sp.C = C;
+    sp.aM = plan->aM;
+    sp.aK = plan->aK;
+    sp.bN = plan->bN;
+    sp.bK = plan->bK;
+    sp.cM = plan->cM;
+    sp.cN = plan->cN;
+    sp.M = info.M;
+    sp.N = info.N;
+    sp.K = info.K;
+    sp.Mp = an.Mp;
+    sp.Np = an.Np;
+    sp.Kp = an.Kp;
+    sp.a_rfast = an.a_mfast;
+    sp.a_kfast = an.a_kfast;
+    sp.b_rfast = an.b_nfast;
+    sp.b_kfast = an.b_kfast;
+    sp.slices = an.slices;
+    sp.fp8 = info.precision == TC_PREC_F64_SPLIT_FP8;
+    char* ws = (char*)workspace;
+    sp.planesA = ws + an.planesA_off;
+    sp.planesB = ws + an.planesB_off;
+    sp.sigA = (double*)(ws + an.sigA_off);
+    sp.sigB = (double*)(ws + an.sigB_off);
+    sp.part = (double*)(ws + an.part_off);
+    sp.alpha = alpha;
+    sp.beta = beta;
+    e = tc::launch_split_contraction(sp, s);
+    return e == hipSuccess ? TC_OK : hip_fail(e, "split-precision launch");
+  }
 
   if (info.recipe == TC_RECIPE_COPY_GEMM && an.copy_slot >= 0) {
     tc::PermuteParams pp{};

@@ -121,17 +121,18 @@ struct Frags {
 };
 
 // Bijective map of the linear workgroup id onto (batch, tile row, tile
-// column).  Workgroups are dealt round-robin to the 8 XCDs; consecutive
-// tiles are gathered on one XCD (sharing its L2), and within an XCD tiles are
-// walked in bands of 8 tile rows so that neighbours reuse A and B rows.
+// column): the batch index is the slowest, tiles within a batch follow the
+// XCD-aware order of xcd_tile.
 __device__ inline void tile_of(int64_t bid, int64_t total, int64_t tilesM, int64_t tilesN, int64_t* l,
                                int64_t* tm, int64_t* tn) {
+  const int64_t per = tilesM * tilesN;
+  // XCD chunks over the whole grid, then split into (batch, tile)
   const int64_t q = total / 8, r = total % 8;
   const int64_t xcd = bid % 8, loc = bid / 8;
   int64_t t = xcd < r ? xcd * (q + 1) + loc : r * (q + 1) + (xcd - r) * q + loc;
-  const int64_t per = tilesM * tilesN;
   *l = t / per;
   t -= *l * per;
+  // banded order inside the batch: identity chunking (xcd_tile with one XCD)
   constexpr int64_t G = 8;
   const int64_t band = t / (G * tilesN);
   const int64_t first = band * G;

@@ -19,6 +19,24 @@ struct Offs {
 
 __host__ __device__ inline int64_t off_at(const Offs& o, int64_t i) { return o.tab ? o.tab[i] : i * o.stride; }
 
+// Bijective map of a linear workgroup id onto (tile row, tile column).
+// Workgroups are dealt round-robin to the 8 XCDs; consecutive tiles are
+// gathered on one XCD (sharing its L2), and within an XCD tiles are walked in
+// bands of 8 tile rows so that neighbours reuse the same rows and columns.
+__device__ inline void xcd_tile(int64_t bid, int64_t total, int64_t tilesM, int64_t tilesN, int64_t* tm,
+                                int64_t* tn) {
+  const int64_t q = total / 8, r = total % 8;
+  const int64_t xcd = bid % 8, loc = bid / 8;
+  int64_t t = xcd < r ? xcd * (q + 1) + loc : r * (q + 1) + (xcd - r) * q + loc;
+  constexpr int64_t G = 8;
+  const int64_t band = t / (G * tilesN);
+  const int64_t first = band * G;
+  const int64_t gs = tilesM - first < G ? tilesM - first : G;
+  const int64_t w = t - band * G * tilesN;
+  *tm = first + w % gs;
+  *tn = w / gs;
+}
+
 // C[m,n,l] = alpha * sum_k A[m,k,l] B[k,n,l] + beta * C[m,n,l] with every
 // operand address split into per-group offsets (A: M,K,L; B: N,K,L; C: M,N,L).
 struct GettParams {
@@ -65,6 +83,45 @@ hipError_t launch_lanes_over_outputs(const GettParams& p, bool n_fastest, hipStr
 hipError_t launch_lanes_over_k(const GettParams& p, int64_t seg, double* part, hipStream_t s);
 // Number of contracted segments the DOT family uses for this many outputs.
 int64_t k_segments(int64_t outputs, int64_t K);
+
+// Split precision: the two inputs are cut into `slices` BF16 or FP8 digit
+// planes (dense, k-contiguous, rows padded to Mp / Np, k padded to Kp) plus
+// per-row power-of-two scales, then multiplied on the matrix cores.
+struct SplitParams {
+  const double* A;
+  const double* B;
+  double* C;
+  Offs aM, aK, bN, bK, cM, cN;
+  int64_t M, N, K, Mp, Np, Kp;
+  bool a_rfast, a_kfast, b_rfast, b_kfast;
+  int slices;
+  bool fp8;
+  void* planesA;
+  void* planesB;
+  double* sigA;
+  double* sigB;
+  double* part;  // max over both inputs of row_max_segments(R, K) * R doubles of scratch
+  double alpha, beta;
+};
+// Contracted segments of the row-maximum pass when rows are stride-1.
+inline int64_t row_max_segments(int64_t R, int64_t K) {
+  int64_t seg = R > 0 ? (262144 + R - 1) / R : 1;
+  const int64_t cap = K / 64 > 1 ? K / 64 : 1;
+  return seg < 1 ? 1 : (seg > cap ? cap : seg);
+}
+constexpr int kSplitMaxBf16 = 7;
+constexpr int kSplitMaxFp8 = 8;
+constexpr int kSplitDefaultBf16 = 5;
+constexpr int kSplitDefaultFp8 = 8;
+struct SplitTile {
+  int bm, bn, bk;
+};
+// Tile of the split GEMM for a digit type and slice count (the LDS holds every
+// slice of a k-step twice over, so more slices need smaller tiles).
+inline constexpr SplitTile split_tile(bool fp8, int slices) {
+  return fp8 ? SplitTile{32, 32, 128} : (slices <= 5 ? SplitTile{128, 64, 32} : SplitTile{64, 64, 32});
+}
+hipError_t launch_split_contraction(const SplitParams& sp, hipStream_t s);
 
 // Y[sum idx_i sy_i] = X[sum idx_i sx_i] over all multi-indices.
 struct PermuteParams {

@@ -193,8 +193,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     }
   }
   if (opt.precision < TC_PREC_F64 || opt.precision > TC_PREC_F64_SPLIT_FP8 || opt.recipe < TC_RECIPE_AUTO ||
-      opt.recipe > TC_RECIPE_DOT || opt.tile_id < -1 || opt.tile_id >= kNumTiles || opt.split_slices < 0 ||
-      opt.split_slices > 8) {
+      opt.recipe > TC_RECIPE_DOT || opt.tile_id < -1 || opt.tile_id >= kNumTiles || opt.split_slices < 0) {
     *err = "invalid tc_options field";
     return TC_ERR_INVALID_ARG;
   }
@@ -307,7 +306,9 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
 
   // COPY_GEMM: copy the input with fewer entries (ties: kernel B) into a
   // packed layout [its free group, contracted group, batch group].
-  if (recipe == TC_RECIPE_COPY_GEMM) an.copy_slot = an.elems[SA] < an.elems[SB] ? SA : SB;
+  // (Split precision gathers both inputs into digit planes: no copy there.)
+  if (recipe == TC_RECIPE_COPY_GEMM && opt.precision == TC_PREC_F64)
+    an.copy_slot = an.elems[SA] < an.elems[SB] ? SA : SB;
   info.copy_operand = an.copy_slot < 0 ? -1 : ((an.copy_slot == SA) != swap ? 0 : 1);
 
   order_group(G[GM], SA, SC);
@@ -363,6 +364,8 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
   bool b_nfast = G[GN].n > 0 && G[GN].str[SB][0] == 1;
   an.a_kfast = !a_mfast && G[GK].n > 0 && G[GK].str[SA][0] == 1;
   an.b_kfast = !b_nfast && G[GK].n > 0 && G[GK].str[SB][0] == 1;
+  an.a_mfast = a_mfast;
+  an.b_nfast = b_nfast;
 
   info.M = G[GM].size();
   info.N = G[GN].size();
@@ -375,7 +378,46 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
   info.nL = G[GL].n;
   info.flops = 2.0 * (double)info.M * (double)info.N * (double)info.K * (double)info.L;
   info.bytes = 8.0 * ((double)product(A0) + (double)product(B0) + (double)product(C0));
-  if (recipe == TC_RECIPE_GEMM || recipe == TC_RECIPE_COPY_GEMM) {
+  if (opt.precision != TC_PREC_F64) {
+    // Split precision: every recipe runs as digit planes (gathered through the
+    // strides once) multiplied on the BF16 / FP8 matrix cores.
+    const bool fp8 = opt.precision == TC_PREC_F64_SPLIT_FP8;
+    const int maxs = fp8 ? kSplitMaxFp8 : kSplitMaxBf16;
+    int S = opt.split_slices > 0 ? opt.split_slices : (fp8 ? kSplitDefaultFp8 : kSplitDefaultBf16);
+    if (S > maxs) {
+      *err = fmt("split_slices %lld exceeds the maximum %lld for this digit type", S, maxs);
+      return TC_ERR_INVALID_ARG;
+    }
+    if (info.L > 1) {
+      *err = "split precision does not take batch indices (labels in A, B and C)";
+      return TC_ERR_UNSUPPORTED;
+    }
+    info.recipe = TC_RECIPE_GEMM;
+    info.split_slices = S;
+    an.slices = S;
+    const SplitTile t = split_tile(fp8, S);
+    auto up = [](int64_t v, int64_t m) { return v <= 0 ? m : (v + m - 1) / m * m; };
+    an.Mp = up(info.M, t.bm);
+    an.Np = up(info.N, t.bn);
+    an.Kp = up(info.K, fp8 ? 128 : t.bk);
+    const size_t esz = fp8 ? 1 : 2;
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    size_t off = 0;
+    an.planesA_off = off;
+    off = al(off + (size_t)S * an.Mp * an.Kp * esz);
+    an.planesB_off = off;
+    off = al(off + (size_t)S * an.Np * an.Kp * esz);
+    an.sigA_off = off;
+    off = al(off + (size_t)an.Mp * sizeof(double));
+    an.sigB_off = off;
+    off = al(off + (size_t)an.Np * sizeof(double));
+    an.part_off = off;
+    // scratch of the row-maximum pass, used by each input in turn
+    const int64_t needA = row_max_segments(info.M, info.K) * info.M;
+    const int64_t needB = row_max_segments(info.N, info.K) * info.N;
+    off = al(off + (size_t)(needA > needB ? needA : needB) * sizeof(double));
+    info.workspace_bytes = off;
+  } else if (recipe == TC_RECIPE_GEMM || recipe == TC_RECIPE_COPY_GEMM) {
     info.tile_id = opt.tile_id >= 0 ? opt.tile_id : pick_tile(info.M, info.N, info.L);
   } else {
     // Memory-bound recipes (Sec. 3.2, Classes 1 and 2, and the GER slicing).

@@ -63,6 +63,12 @@ struct Analysis {
   bool n_fastest = false;   // lanes-over-outputs: consecutive lanes along n
   int64_t seg = 1;          // lanes-over-k: contracted segments per output
   size_t part_offset = 0;   // byte offset of the partial sums in the workspace
+  bool a_mfast = false;     // kernel A's stride-1 mode leads its free group
+  bool b_nfast = false;     // kernel B's stride-1 mode leads its free group
+  // split precision: padded sizes of the digit planes and workspace offsets
+  int slices = 0;
+  int64_t Mp = 0, Np = 0, Kp = 0;
+  size_t planesA_off = 0, planesB_off = 0, sigA_off = 0, sigB_off = 0, part_off = 0;
   int64_t elems[3] = {};    // entries of kernel A, kernel B, C (products of extents)
   // COPY_GEMM: the copied operand (kernel slot) and its modes before and after
   // the copy, in the copied tensor's own storage order.

@@ -1,0 +1,530 @@
+// Split-precision contraction: FP64 accuracy from BF16 (or FP8) matrix cores.
+//
+// Scheme (error-free splitting in the manner of Ozaki, Ogita, Oishi and Rump,
+// 2012; written from the mathematics, not from any code):
+//   * each row r of the gathered A (and each column of B) gets a power-of-two
+//     scale sigma_r >= max_k |X[r,k]|, so every x / sigma_r lies in (-1, 1);
+//   * that ratio is cut into S integer digits: q_0 = rint(2^b x/sigma), then
+//     each remainder (at most 1/2 in magnitude) is multiplied by 2^(b+1) and
+//     rounded again, so |q_s| <= 2^b and x = sigma * sum_s q_s 2^(-b-(b+1)s)
+//     up to the last remainder.  b = 8 for BF16 (integers up to 256 are exact
+//     there) and b = 4 for FP8 E4M3 (integers up to 16);
+//   * C = sum over digit pairs (s, t) with s + t < S of the digit products.
+//     Products of one "level" g = s + t carry the same power of two.  Every
+//     digit product is an integer below 2^(2b), so sums of a few hundred of
+//     them are exact in FP32: the sums of levels 0, 1 and 2 are kept in their
+//     own FP32 accumulators and moved to FP64 every 64 contracted indices,
+//     which keeps them exact; the deeper levels (2^-27 and below) share one
+//     FP32 accumulator whose rounding is far below the target accuracy.
+//   * BF16 planes are stored pre-scaled by 2^(-9(s-1)), so that every product
+//     of planes s and t carries the same factor 2^(-34) sigma_m tau_n; the FP8
+//     planes keep the raw digits and pass the per-plane powers of two as the
+//     matrix-core block scales.
+// The digits are written densely, k-contiguous and digit-interleaved per
+// k-step ([row][k-step][s][k]); gathering the tensor through its strides
+// happens once, in the split pass.
+#include "kernels.hpp"
+
+namespace tc {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef int i8v __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline int fq_of(int lane) { return lane >> 4; }
+
+// ---------------------------------------------------------------- scales
+// sigma[r] = 2^e with max_k |X[r,k]| < 2^e (0 for an all-zero row or padding).
+__device__ inline double pow2_above(double mx) {
+  if (mx == 0.0) return 0.0;
+  int e;
+  (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)
+  return ldexp(1.0, e);
+}
+
+// Rows stride-1 in memory: one thread per row walks one segment of k and
+// writes a partial maximum; a second pass takes the maximum over segments.
+__global__ __launch_bounds__(256) void row_max_rows_kernel(const double* __restrict__ X, Offs xr, Offs xk,
+                                                           int64_t R, int64_t K, int64_t seg_len,
+                                                           double* __restrict__ part) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t sgi = blockIdx.y;
+  if (r >= R) return;
+  const double* row = X + off_at(xr, r);
+  const int64_t k0 = sgi * seg_len, k1 = k0 + seg_len < K ? k0 + seg_len : K;
+  double mx = 0.0;
+  for (int64_t k = k0; k < k1; ++k) mx = fmax(mx, fabs(row[off_at(xk, k)]));
+  part[sgi * R + r] = mx;
+}
+
+__global__ __launch_bounds__(256) void row_scale_from_parts_kernel(const double* __restrict__ part, int64_t R,
+                                                                   int64_t nseg, int64_t Rp,
+                                                                   double* __restrict__ sigma) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= Rp) return;
+  double mx = 0.0;
+  if (r < R)
+    for (int64_t g = 0; g < nseg; ++g) mx = fmax(mx, part[g * R + r]);
+  sigma[r] = pow2_above(mx);
+}
+
+// One wavefront per row, lanes along k (k stride-1 in memory).
+__global__ __launch_bounds__(256) void row_scale_wave_kernel(const double* __restrict__ X, Offs xr, Offs xk,
+                                                             int64_t R, int64_t K, int64_t Rp,
+                                                             double* __restrict__ sigma) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= Rp) return;
+  double mx = 0.0;
+  if (r < R) {
+    const double* row = X + off_at(xr, r);
+    for (int64_t k = lane; k < K; k += 64) mx = fmax(mx, fabs(row[off_at(xk, k)]));
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) sigma[r] = pow2_above(mx);
+}
+
+// ---------------------------------------------------------------- digits
+__device__ inline u16 bf16_bits_of_small_int(double v, int scale_exp) {
+  // v is an integer with |v| <= 256; v * 2^scale_exp is exact in BF16
+  float f = ldexpf((float)v, scale_exp);
+  unsigned u = __float_as_uint(f);
+  return (u16)(u >> 16);  // exact: the low 16 bits are zero
+}
+
+// E4M3 (OCP) bits of an integer v with |v| <= 16.
+__device__ inline unsigned char e4m3_of_small_int(int v) {
+  if (v == 0) return 0;
+  unsigned char s = v < 0 ? 0x80 : 0;
+  int a = v < 0 ? -v : v;
+  int e = 31 - __clz(a);                  // a in [2^e, 2^(e+1))
+  int m = ((a - (1 << e)) << 3) >> e;     // 3 mantissa bits, exact for a <= 16
+  return s | (unsigned char)(((e + 7) << 3) | m);
+}
+
+// Digits of a 64 x 64 tile of X staged in LDS; rows beyond R and columns
+// beyond K are written as zero digits.
+template <int S, bool FP8>
+__global__ __launch_bounds__(256) void split_planes_kernel(const double* __restrict__ X, Offs xr, Offs xk,
+                                                           int64_t R, int64_t K, int64_t Rp, int64_t Kp,
+                                                           const double* __restrict__ sigma, int rfast,
+                                                           void* __restrict__ planes) {
+  __shared__ double tile[64][65];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * 64, k0 = (int64_t)blockIdx.x * 64;
+  if (rfast) {
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+      const int rr = tid & 63, kk = (tid >> 6) + 4 * i;
+      const int64_t r = r0 + rr, k = k0 + kk;
+      tile[rr][kk] = (r < R && k < K) ? X[off_at(xr, r) + off_at(xk, k)] : 0.0;
+    }
+  } else {
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+      const int kk = tid & 63, rr = (tid >> 6) + 4 * i;
+      const int64_t r = r0 + rr, k = k0 + kk;
+      tile[rr][kk] = (r < R && k < K) ? X[off_at(xr, r) + off_at(xk, k)] : 0.0;
+    }
+  }
+  __syncthreads();
+  constexpr double first = FP8 ? 16.0 : 256.0;   // 2^b
+  constexpr double next = FP8 ? 32.0 : 512.0;    // 2^(b+1)
+  const int kk = tid & 63;
+#pragma unroll 2
+  for (int i = 0; i < 16; ++i) {
+    const int rr = (tid >> 6) + 4 * i;
+    const int64_t r = r0 + rr, k = k0 + kk;
+    if (r >= Rp || k >= Kp) continue;
+    const double sg = sigma[r];
+    double rem = sg > 0.0 ? tile[rr][kk] / sg : 0.0;  // exact: sg is a power of two
+    // digit-interleaved layout [r][k / KB][s][k % KB]: one k-step of a row
+    // holds all S digits contiguously (whole cache lines per load)
+    constexpr int KB = FP8 ? 128 : 32;
+    const int64_t base = r * Kp * S + (k / KB) * (S * KB) + (k % KB);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double y = rem * (s == 0 ? first : next);
+      const double q = rint(y);
+      rem = y - q;  // exact
+      if constexpr (FP8) {
+        ((unsigned char*)planes)[base + s * KB] = e4m3_of_small_int((int)q);
+      } else {
+        ((u16*)planes)[base + s * KB] = bf16_bits_of_small_int(q, -9 * (s - 1));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- GEMM
+struct SplitGemmArgs {
+  const void* pa;        // digits of the kernel's A: [Mp][Kp/KB][S][KB]
+  const void* pb;        // digits of the kernel's B: [Np][Kp/KB][S][KB]
+  const double* sa;      // sigma of A rows (Mp)
+  const double* sb;      // sigma of B rows (Np)
+  double* C;
+  Offs cM, cN;
+  int64_t M, N, Mp, Np, Kp;
+  double alpha, beta;
+  double unit;           // power of two turning the accumulated digit sums into values
+};
+
+// Register stage of one k-step: each thread moves CPT 16-byte chunks from
+// global memory (row pointers fixed per tile, advanced by the k offset) to
+// precomputed LDS offsets.  Kept in a struct with constant-indexed arrays so
+// that the chunks stay in registers while the MFMAs of the current k-step run.
+template <typename T, int CPT, int CHUNKS, int NT>
+struct Stager {
+  u32x4 v[CPT];
+  int dst[CPT];
+  __device__ inline void load(const T* const (&row)[CPT], int64_t koff, int tid) {
+#pragma unroll
+    for (int i = 0; i < CPT; ++i)
+      if (CHUNKS % NT == 0 || tid + i * NT < CHUNKS) v[i] = *(const u32x4*)(row[i] + koff);
+  }
+  __device__ inline void store(T* st, int tid) const {
+#pragma unroll
+    for (int i = 0; i < CPT; ++i)
+      if (CHUNKS % NT == 0 || tid + i * NT < CHUNKS) *(u32x4*)(st + dst[i]) = v[i];
+  }
+};
+
+// BF16 digits: v_mfma_f32_16x16x32_bf16.  Operand lane layout (measured):
+// lane l holds A[l%16][8(l/16) .. 8(l/16)+7] and B[8(l/16) ..][l%16]; the
+// accumulator element r holds D[4(l/16) + r][l%16].
+template <int BM, int BN, int WGM, int WGN, int S>
+__global__ __launch_bounds__(64 * WGM * WGN) void split_gemm_bf16_kernel(SplitGemmArgs p) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int BK = 32;                  // one MFMA depth per k-step
+  constexpr int ROW = S * BK;             // bf16 per staged row: all S digits of one k-step
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int CPR = S * 4;                            // 16-byte chunks per staged row
+  constexpr int CHUNKS = (BM + BN) * CPR;
+  constexpr int CPT = (CHUNKS + NT - 1) / NT;           // chunks per thread
+  __shared__ __attribute__((aligned(16))) u16 sm[2][(BM + BN) * ROW];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  int64_t tm, tn;
+  xcd_tile(blockIdx.x, (p.Mp / BM) * (p.Np / BN), p.Mp / BM, p.Np / BN, &tm, &tn);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+
+  const u16* __restrict__ PA = (const u16*)p.pa;
+  const u16* __restrict__ PB = (const u16*)p.pb;
+  const int64_t rowlen = p.Kp * S;  // digits per row of the dense digit matrix
+
+  // Staged row r keeps its 16-byte chunk q of digit s at slot q ^ ((r >> 2) & 3):
+  // the 16 rows one fragment read touches then fall in 16 distinct bank groups.
+  auto lds_off = [](int r, int s_, int q) { return r * ROW + s_ * BK + ((q ^ ((r >> 2) & 3)) << 3); };
+  Stager<u16, CPT, CHUNKS, NT> stg;
+  const u16* srow[CPT];
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int c = tid + i * NT;
+    const int row = (c < CHUNKS ? c : 0) / CPR, sub = (c < CHUNKS ? c : 0) % CPR;
+    srow[i] = (row < BM ? PA + (m0 + row) * rowlen : PB + (n0 + row - BM) * rowlen) + sub * 8;
+    stg.dst[i] = lds_off(row, sub >> 2, sub & 3);
+  }
+
+  // Level g (digit pair s + t = g) sums: levels 0, 1, 2 exact in their own
+  // accumulators over 64 contracted indices (at most 3 * 64 * 2^16 < 2^24 digit
+  // units), deeper levels together.
+  constexpr int NACC = S < 4 ? S : 4;
+  f4 acc[NACC][TM][TN];
+  double acc64[TM][TN][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+#pragma unroll
+      for (int g = 0; g < NACC; ++g) acc[g][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+    }
+
+  const int64_t ksteps = p.Kp / BK;
+  stg.load(srow, 0, tid);
+  stg.store(sm[0], tid);
+  __syncthreads();
+  const int fr = lane & 15, fq = lane >> 4;
+  for (int64_t ks = 0; ks < ksteps; ++ks) {
+    const int cur = ks & 1;
+    if (ks + 1 < ksteps) stg.load(srow, (ks + 1) * ROW, tid);
+    const u16* st = sm[cur];
+    bf8 af[S][TM];
+#pragma unroll
+    for (int s_ = 0; s_ < S; ++s_)
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[s_][i] = *(const bf8*)(st + lds_off(wm * WM + i * 16 + fr, s_, fq));
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      bf8 bfr[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bfr[j] = *(const bf8*)(st + lds_off(BM + wn * WN + j * 16 + fr, t, fq));
+#pragma unroll
+      for (int s_ = 0; s_ + t < S; ++s_) {
+        const int g = s_ + t < NACC ? s_ + t : NACC - 1;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[g][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s_][i], bfr[j], acc[g][i][j], 0, 0, 0);
+      }
+    }
+    // move the FP32 sums to FP64 every 64 contracted indices (and at the end)
+    if ((ks & 1) == 1 || ks + 1 == ksteps) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double v = 0.0;
+#pragma unroll
+            for (int g = NACC - 1; g >= 0; --g) v += (double)acc[g][i][j][r];
+            acc64[i][j][r] += v;
+          }
+#pragma unroll
+          for (int g = 0; g < NACC; ++g) acc[g][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    if (ks + 1 < ksteps) stg.store(sm[cur ^ 1], tid);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = m0 + wm * WM + i * 16 + fq * 4 + r;
+      if (m >= p.M) continue;
+      const double sm_ = p.sa[m] * p.unit * p.alpha;
+      const int64_t cm = off_at(p.cM, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t n = n0 + wn * WN + j * 16 + fr;
+        if (n >= p.N) continue;
+        double* dst = p.C + cm + off_at(p.cN, n);
+        double v = sm_ * p.sb[n] * acc64[i][j][r];
+        if (p.beta != 0.0) v += p.beta * *dst;
+        *dst = v;
+      }
+    }
+  }
+}
+
+// FP8 E4M3 digits: v_mfma_scale_f32_16x16x128_f8f6f4 with the per-plane powers
+// of two as E8M0 block scales.  Lane l holds A[l%16][32(l/16) .. +31]; the
+// accumulator element r holds D[4(l/16) + r][l%16].
+template <int BM, int BN, int WGM, int WGN, int S>
+__global__ __launch_bounds__(64 * WGM * WGN) void split_gemm_fp8_kernel(SplitGemmArgs p) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int BK = 128;                        // one MFMA depth per k-step (bytes = digits)
+  constexpr int ROW = S * BK + (S % 2 ? 0 : BK);  // bytes per staged row (odd multiple of 128)
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int CPR = S * 8;
+  constexpr int CHUNKS = (BM + BN) * CPR;
+  constexpr int CPT = (CHUNKS + NT - 1) / NT;
+  __shared__ __attribute__((aligned(16))) unsigned char sm[2][(BM + BN) * ROW];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  int64_t tm, tn;
+  xcd_tile(blockIdx.x, (p.Mp / BM) * (p.Np / BN), p.Mp / BM, p.Np / BN, &tm, &tn);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const unsigned char* __restrict__ PA = (const unsigned char*)p.pa;
+  const unsigned char* __restrict__ PB = (const unsigned char*)p.pb;
+  const int64_t rowlen = p.Kp * S;
+
+  // chunk q of digit s of staged row r sits at slot q ^ ((r >> 1) & 7)
+  auto lds_off = [](int r, int s_, int q) { return r * ROW + s_ * BK + ((q ^ ((r >> 1) & 7)) << 4); };
+  Stager<unsigned char, CPT, CHUNKS, NT> stg;
+  const unsigned char* srow[CPT];
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int c = tid + i * NT;
+    const int row = (c < CHUNKS ? c : 0) / CPR, sub = (c < CHUNKS ? c : 0) % CPR;
+    srow[i] = (row < BM ? PA + (m0 + row) * rowlen : PB + (n0 + row - BM) * rowlen) + sub * 16;
+    stg.dst[i] = lds_off(row, sub >> 3, sub & 7);
+  }
+  auto frag = [&](const unsigned char* st, int row, int s_) -> i8v {
+    const u32x4 lo = *(const u32x4*)(st + lds_off(row, s_, 2 * fq_of(lane)));
+    const u32x4 hi = *(const u32x4*)(st + lds_off(row, s_, 2 * fq_of(lane) + 1));
+    return i8v{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+  };
+
+  // Every FP8 digit product is an integer below 2^8 times the block scales
+  // (which put each level at its true relative weight 2^(-5g)).  Levels 0 to 4
+  // keep their own FP32 accumulators, exact for 4096 contracted indices
+  // ((g+1) 4096 2^8 < 2^24); deeper levels (2^-25 and below) share one.
+  // Flushed to FP64 every 4096.
+  constexpr int NACC = S < 6 ? S : 6;
+  f4 acc[NACC][TM][TN];
+  double acc64[TM][TN][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+#pragma unroll
+      for (int g = 0; g < NACC; ++g) acc[g][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+    }
+  const int64_t ksteps = p.Kp / BK;
+  stg.load(srow, 0, tid);
+  stg.store(sm[0], tid);
+  __syncthreads();
+  const int fr = lane & 15, fq = lane >> 4;
+  for (int64_t ks = 0; ks < ksteps; ++ks) {
+    const int cur = ks & 1;
+    if (ks + 1 < ksteps) stg.load(srow, (ks + 1) * (S * BK), tid);
+    const unsigned char* st = sm[cur];
+    i8v af[S][TM];
+#pragma unroll
+    for (int s_ = 0; s_ < S; ++s_)
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[s_][i] = frag(st, wm * WM + i * 16 + fr, s_);
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      i8v bfr[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bfr[j] = frag(st, BM + wn * WN + j * 16 + fr, t);
+#pragma unroll
+      for (int s_ = 0; s_ + t < S; ++s_) {
+        // digit plane s carries 2^(-5s): E8M0 scale 127 - 5s (127 = 2^0)
+        const int g = s_ + t < NACC ? s_ + t : NACC - 1;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[g][i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[s_][i], bfr[j], acc[g][i][j], 0, 0, 0,
+                                                                          127 - 5 * s_, 0, 127 - 5 * t);
+      }
+    }
+    if ((ks & 31) == 31 || ks + 1 == ksteps) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double v = 0.0;
+#pragma unroll
+            for (int g = NACC - 1; g >= 0; --g) v += (double)acc[g][i][j][r];
+            acc64[i][j][r] += v;
+          }
+#pragma unroll
+          for (int g = 0; g < NACC; ++g) acc[g][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    if (ks + 1 < ksteps) stg.store(sm[cur ^ 1], tid);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = m0 + wm * WM + i * 16 + fq * 4 + r;
+      if (m >= p.M) continue;
+      const double sm_ = p.sa[m] * p.unit * p.alpha;
+      const int64_t cm = off_at(p.cM, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t n = n0 + wn * WN + j * 16 + fr;
+        if (n >= p.N) continue;
+        double* dst = p.C + cm + off_at(p.cN, n);
+        double v = sm_ * p.sb[n] * acc64[i][j][r];
+        if (p.beta != 0.0) v += p.beta * *dst;
+        *dst = v;
+      }
+    }
+  }
+}
+
+template <int S>
+hipError_t launch_planes(const double* X, Offs xr, Offs xk, int64_t R, int64_t K, int64_t Rp, int64_t Kp,
+                         double* sigma, double* part, bool rfast, bool kfast, bool fp8, void* planes,
+                         hipStream_t s) {
+  if (kfast && !rfast) {
+    hipLaunchKernelGGL(row_scale_wave_kernel, dim3((unsigned)((Rp + 3) / 4)), dim3(256), 0, s, X, xr, xk, R, K, Rp,
+                       sigma);
+  } else {
+    const int64_t nseg = row_max_segments(R, K);
+    const int64_t seg_len = (K + nseg - 1) / nseg;
+    if (R > 0)
+      hipLaunchKernelGGL(row_max_rows_kernel, dim3((unsigned)((R + 255) / 256), (unsigned)nseg), dim3(256), 0, s, X,
+                         xr, xk, R, K, seg_len, part);
+    hipLaunchKernelGGL(row_scale_from_parts_kernel, dim3((unsigned)((Rp + 255) / 256)), dim3(256), 0, s, part, R,
+                       nseg, Rp, sigma);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)((Kp + 63) / 64), (unsigned)((Rp + 63) / 64));
+  if (fp8)
+    hipLaunchKernelGGL((split_planes_kernel<S, true>), grid, dim3(256), 0, s, X, xr, xk, R, K, Rp, Kp, sigma,
+                       rfast ? 1 : 0, planes);
+  else
+    hipLaunchKernelGGL((split_planes_kernel<S, false>), grid, dim3(256), 0, s, X, xr, xk, R, K, Rp, Kp, sigma,
+                       rfast ? 1 : 0, planes);
+  return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_split_gemm(const SplitGemmArgs& a, bool fp8, hipStream_t s) {
+  const SplitTile t = split_tile(fp8, S);
+  const dim3 grid((unsigned)((a.Mp / t.bm) * (a.Np / t.bn)));
+  if (fp8) {
+    if constexpr (S <= kSplitMaxFp8)
+      hipLaunchKernelGGL((split_gemm_fp8_kernel<32, 32, 2, 2, S>), grid, dim3(256), 0, s, a);
+    else
+      return hipErrorInvalidValue;
+  } else if constexpr (S <= 5) {
+    hipLaunchKernelGGL((split_gemm_bf16_kernel<128, 64, 4, 2, S>), grid, dim3(512), 0, s, a);
+  } else if constexpr (S <= kSplitMaxBf16) {
+    hipLaunchKernelGGL((split_gemm_bf16_kernel<64, 64, 2, 2, S>), grid, dim3(256), 0, s, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_split_contraction(const SplitParams& sp, hipStream_t s) {
+  const int S = sp.slices;
+  const bool fp8 = sp.fp8;
+  hipError_t e = hipSuccess;
+#define TC_SPLIT_CASE(NS)                                                                                        \
+  case NS:                                                                                                       \
+    e = launch_planes<NS>(sp.A, sp.aM, sp.aK, sp.M, sp.K, sp.Mp, sp.Kp, sp.sigA, sp.part, sp.a_rfast, sp.a_kfast, \
+                          fp8, sp.planesA, s);                                                                   \
+    if (e != hipSuccess) return e;                                                                               \
+    e = launch_planes<NS>(sp.B, sp.bN, sp.bK, sp.N, sp.K, sp.Np, sp.Kp, sp.sigB, sp.part, sp.b_rfast, sp.b_kfast, \
+                          fp8, sp.planesB, s);                                                                   \
+    if (e != hipSuccess) return e;                                                                               \
+    {                                                                                                            \
+      SplitGemmArgs a{sp.planesA, sp.planesB, sp.sigA, sp.sigB, sp.C,  sp.cM, sp.cN,     sp.M,                   \
+                      sp.N,       sp.Mp,      sp.Np,   sp.Kp,   sp.alpha, sp.beta, fp8 ? 0x1p-8 : 0x1p-34};      \
+      return launch_split_gemm<NS>(a, fp8, s);                                                                   \
+    }
+  switch (S) {
+    TC_SPLIT_CASE(1)
+    TC_SPLIT_CASE(2)
+    TC_SPLIT_CASE(3)
+    TC_SPLIT_CASE(4)
+    TC_SPLIT_CASE(5)
+    TC_SPLIT_CASE(6)
+    TC_SPLIT_CASE(7)
+    TC_SPLIT_CASE(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef TC_SPLIT_CASE
+}
+
+}  // namespace tc

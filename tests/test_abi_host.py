@@ -209,3 +209,15 @@ def test_single_hip_runtime_in_process():
     maps = open("/proc/self/maps").read()
     libs = set(l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l)
     assert len(libs) == 1, libs
+
+
+def test_split_precision_plans_have_no_copy_step():
+    """Split precision gathers both inputs into digit planes itself: even a
+    Class 3.1 contraction gets no COPY step (its operand strides must stay the
+    caller's)."""
+    ext = {l: 6 for l in "abgh"}
+    info = analyze("abg", "gah", "bh", ext, precision="split_bf16")
+    assert info.paper_class == 31 and info.copy_operand == -1 and info.split_slices == 5
+    assert info.workspace_bytes > 0
+    info = analyze("abg", "gah", "bh", ext, precision="split_fp8")
+    assert info.split_slices == 8
