@@ -104,7 +104,9 @@ typedef struct {
   double bytes;                /* 8 (|A| + |B| + |C|): algorithmic traffic with beta = 0 */
   size_t workspace_bytes;      /* device workspace tc_execute needs (0 = none) */
   tc_precision precision;
-  int split_slices;
+  int split_slices;            /* digits per input (split precision), 0 otherwise */
+  int kernel;                  /* kernel family: 0 MFMA GEMM, 1 lanes over outputs, 2 lanes over k,
+                                  3 batched small slabs, 4 split-precision digits */
 } tc_plan_info;
 
 /* Fills *opt with the defaults listed in tc_options. */
@@ -152,17 +154,35 @@ tc_status tc_plan_destroy(tc_plan_t plan);
 tc_status tc_permute(int rank, const int64_t* ext, const int64_t* str_x, const int64_t* str_y,
                      const double* X, double* Y, void* stream);
 
-/* Batches (many independent contractions in one persistent launch).
- * tc_batch_create takes n plans (FP64, any recipe), which must outlive the
- * batch.  tc_batch_execute runs C_i <- alpha_i * sum A_i*B_i + beta_i C_i for
- * all i in one kernel launch; A, B, C, alpha, beta are HOST arrays of n
- * entries holding device pointers / scalars.  The workspace must hold
- * tc_batch_workspace() bytes. */
+/* Batches: many independent FP64 contractions of any shapes run by one
+ * persistent kernel launch (an addition to the paper; its general-relativity
+ * workload, Sec. 4.2, is the model of the batch-dominated entries).
+ * tc_batch_create takes n >= 1 plans on the current device; the batch copies
+ * what it needs, so the plans may be destroyed afterwards.  Each contraction
+ * runs as FP64 MFMA GEMM tiles, or, when its batch indices dominate, as slabs
+ * of batch indices; split precision plans are rejected (TC_ERR_UNSUPPORTED).
+ * tc_batch_execute runs C_i <- alpha_i * sum A_i*B_i + beta_i * C_i for every
+ * i: A, B, C, alpha and beta are HOST arrays of n entries (device pointers and
+ * scalars).  The workspace (device, tc_batch_workspace bytes) holds the
+ * pointers and the task counter.  By default the launch sequence is captured
+ * once in a hipGraph and replayed; executions of one batch must not overlap
+ * (the call waits until the previous execution has read its inputs). */
 tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans);
 tc_status tc_batch_workspace(tc_batch_t batch, size_t* bytes);
 tc_status tc_batch_execute(tc_batch_t batch, const double* const* A, const double* const* B,
                            double* const* C, const double* alpha, const double* beta,
                            void* workspace, size_t workspace_bytes, void* stream);
+/* tile_config: -1 keeps the current one, else 0..3 (64x64, 32x32, 128x64,
+ * 64x128 GEMM tiles); use_graph: 0 launches eagerly, 1 replays a hipGraph. */
+tc_status tc_batch_set_options(tc_batch_t batch, int tile_config, int use_graph);
+tc_status tc_batch_query(tc_batch_t batch, int64_t* ntasks, int* tile_config, int* use_graph);
+/* Autotuner: times every tile configuration on the given buffers (C is
+ * overwritten; eager launches, median of three) and keeps the fastest, which
+ * it returns in *best_config with its time in *best_ms (either may be NULL). */
+tc_status tc_batch_autotune(tc_batch_t batch, const double* const* A, const double* const* B,
+                            double* const* C, const double* alpha, const double* beta,
+                            void* workspace, size_t workspace_bytes, void* stream,
+                            int* best_config, double* best_ms);
 tc_status tc_batch_destroy(tc_batch_t batch);
 
 const char* tc_status_string(tc_status s);

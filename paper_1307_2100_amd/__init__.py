@@ -42,6 +42,7 @@ PRECISIONS = {"f64": 0, "split_bf16": 1, "split_fp8": 2}
 TC_RECIPE_AUTO, TC_RECIPE_GEMM, TC_RECIPE_COPY_GEMM, TC_RECIPE_GEMV, TC_RECIPE_GER, TC_RECIPE_DOT = range(6)
 RECIPES = {"auto": 0, "gemm": 1, "copy_gemm": 2, "gemv": 3, "ger": 4, "dot": 5}
 RECIPE_NAMES = {v: k for k, v in RECIPES.items()}
+KERNEL_NAMES = {0: "mfma_gemm", 1: "lanes_over_outputs", 2: "lanes_over_k", 3: "batched_small", 4: "split_digits"}
 # GEMM tile configurations compiled into libtc (ids 0 .. NUM_TILES-1)
 NUM_TILES = 14
 # tc_picker
@@ -61,11 +62,12 @@ class tc_plan_info(ctypes.Structure):
                 ("nM", ctypes.c_int), ("nN", ctypes.c_int), ("nK", ctypes.c_int), ("nL", ctypes.c_int),
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t), ("precision", ctypes.c_int),
-                ("split_slices", ctypes.c_int)]
+                ("split_slices", ctypes.c_int), ("kernel", ctypes.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["recipe_name"] = RECIPE_NAMES.get(self.recipe, "?")
+        d["kernel_name"] = KERNEL_NAMES.get(self.kernel, "?")
         return d
 
 
@@ -97,6 +99,14 @@ _lib.tc_batch_execute.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_
                                   ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]
 _lib.tc_batch_execute.restype = ctypes.c_int
+_lib.tc_batch_set_options.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+_lib.tc_batch_set_options.restype = ctypes.c_int
+_lib.tc_batch_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int)]
+_lib.tc_batch_query.restype = ctypes.c_int
+_lib.tc_batch_autotune.argtypes = _lib.tc_batch_execute.argtypes + [ctypes.POINTER(ctypes.c_int),
+                                                                    ctypes.POINTER(ctypes.c_double)]
+_lib.tc_batch_autotune.restype = ctypes.c_int
 _lib.tc_batch_destroy.argtypes = [ctypes.c_void_p]
 _lib.tc_batch_destroy.restype = ctypes.c_int
 _lib.tc_status_string.argtypes = [ctypes.c_int]
@@ -106,7 +116,8 @@ _lib.tc_version.restype = ctypes.c_char_p
 
 EXPORTED = ["tc_options_default", "tc_analyze", "tc_plan_create", "tc_plan_query", "tc_execute",
             "tc_plan_destroy", "tc_permute", "tc_batch_create", "tc_batch_workspace", "tc_batch_execute",
-            "tc_batch_destroy", "tc_status_string", "tc_last_error", "tc_version"]
+            "tc_batch_set_options", "tc_batch_query", "tc_batch_autotune", "tc_batch_destroy",
+            "tc_status_string", "tc_last_error", "tc_version"]
 
 
 class TCError(RuntimeError):
@@ -322,3 +333,75 @@ def permute(X, strides_out, Y):
     tc_permute(list(X.shape), list(X.stride()), list(strides_out), ctypes.c_void_p(X.data_ptr()),
                ctypes.c_void_p(Y.data_ptr()), _stream_handle())
     return Y
+
+
+# ------------------------------------------------------------------- batches
+class Batch:
+    """A libtc batch: many contractions run by one persistent kernel launch."""
+
+    def __init__(self, plans):
+        self.n = len(plans)
+        arr = (ctypes.c_void_p * self.n)(*[p.handle.value if isinstance(p, Plan) else p for p in plans])
+        h = ctypes.c_void_p()
+        _check(_lib.tc_batch_create(ctypes.byref(h), self.n, arr))
+        self.handle = h
+        nb = ctypes.c_size_t()
+        _check(_lib.tc_batch_workspace(h, ctypes.byref(nb)))
+        self.workspace_bytes = nb.value
+        self._ws = None
+
+    def workspace(self, device=None):
+        torch = _torch()
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device or "cuda")
+        return self._ws
+
+    def _arrays(self, As, Bs, Cs, alphas, betas):
+        n = self.n
+        if not (len(As) == len(Bs) == len(Cs) == n):
+            raise ValueError("need %d operand triples" % n)
+        alphas = [1.0] * n if alphas is None else list(alphas)
+        betas = [0.0] * n if betas is None else list(betas)
+        a = (ctypes.c_void_p * n)(*[t.data_ptr() for t in As])
+        b = (ctypes.c_void_p * n)(*[t.data_ptr() for t in Bs])
+        c = (ctypes.c_void_p * n)(*[t.data_ptr() for t in Cs])
+        al = (ctypes.c_double * n)(*alphas)
+        be = (ctypes.c_double * n)(*betas)
+        return a, b, c, al, be
+
+    def execute(self, As, Bs, Cs, alphas=None, betas=None, stream=None):
+        a, b, c, al, be = self._arrays(As, Bs, Cs, alphas, betas)
+        ws = self.workspace(Cs[0].device)
+        _check(_lib.tc_batch_execute(self.handle, a, b, c, al, be, ctypes.c_void_p(ws.data_ptr()),
+                                     self.workspace_bytes, _stream_handle(stream)))
+
+    def autotune(self, As, Bs, Cs, alphas=None, betas=None, stream=None):
+        a, b, c, al, be = self._arrays(As, Bs, Cs, alphas, betas)
+        ws = self.workspace(Cs[0].device)
+        best = ctypes.c_int()
+        ms = ctypes.c_double()
+        _check(_lib.tc_batch_autotune(self.handle, a, b, c, al, be, ctypes.c_void_p(ws.data_ptr()),
+                                      self.workspace_bytes, _stream_handle(stream), ctypes.byref(best),
+                                      ctypes.byref(ms)))
+        return best.value, ms.value
+
+    def set_options(self, tile_config=-1, use_graph=1):
+        _check(_lib.tc_batch_set_options(self.handle, int(tile_config), int(use_graph)))
+
+    def query(self):
+        nt = ctypes.c_int64()
+        cfg = ctypes.c_int()
+        g = ctypes.c_int()
+        _check(_lib.tc_batch_query(self.handle, ctypes.byref(nt), ctypes.byref(cfg), ctypes.byref(g)))
+        return {"ntasks": nt.value, "tile_config": cfg.value, "use_graph": g.value}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            _lib.tc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

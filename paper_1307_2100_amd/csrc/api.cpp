@@ -41,7 +41,8 @@ tc_status fill_desc(tc::TensorDesc* d, int rank, const int64_t* ext, const int64
 
 tc_status analyze_args(int ra, const int64_t* ea, const int64_t* sa, const int32_t* la, int rb, const int64_t* eb,
                        const int64_t* sb, const int32_t* lb, int rc, const int64_t* ec, const int64_t* sc,
-                       const int32_t* lc, const tc_options* opt, tc::Analysis* an) {
+                       const int32_t* lc, const tc_options* opt, tc::Analysis* an, tc::TensorDesc* keep = nullptr,
+                       tc_options* keep_opt = nullptr) {
   tc::TensorDesc A, B, C;
   tc_status s;
   if ((s = fill_desc(&A, ra, ea, sa, la, "A")) != TC_OK) return s;
@@ -53,6 +54,61 @@ tc_status analyze_args(int ra, const int64_t* ea, const int64_t* sa, const int32
   std::string err;
   s = tc::analyze(A, B, C, o, an, &err);
   if (s != TC_OK) return fail(s, err);
+  if (keep) {
+    keep[0] = A;
+    keep[1] = B;
+    keep[2] = C;
+  }
+  if (keep_opt) *keep_opt = o;
+  return TC_OK;
+}
+
+// Offset tables of an analysis: one per (group, operand) with more than one
+// mode, appended to `host`; a group of zero or one mode is affine.  `pos`
+// pairs each table-backed Offs with its start in `host`, to be pointed at the
+// device copy once uploaded.
+struct OffsTargets {
+  tc::Offs *aM, *aK, *aL, *bN, *bK, *bL, *cM, *cN, *cL;
+};
+void build_tables(const tc::Analysis& an, const OffsTargets& t, std::vector<int64_t>& host,
+                  std::vector<std::pair<tc::Offs*, size_t>>& pos) {
+  const tc::Group* G = an.g;
+  struct Want {
+    int group, slot;
+    tc::Offs* dst;
+  } want[9] = {{tc::GM, tc::SA, t.aM}, {tc::GK, tc::SA, t.aK}, {tc::GL, tc::SA, t.aL},
+               {tc::GN, tc::SB, t.bN}, {tc::GK, tc::SB, t.bK}, {tc::GL, tc::SB, t.bL},
+               {tc::GM, tc::SC, t.cM}, {tc::GN, tc::SC, t.cN}, {tc::GL, tc::SC, t.cL}};
+  for (int w = 0; w < 9; ++w) {
+    const tc::Group& g = G[want[w].group];
+    if (g.n <= 1 || an.empty_out) {
+      want[w].dst->tab = nullptr;
+      want[w].dst->stride = g.n == 1 ? g.str[want[w].slot][0] : 0;
+      continue;
+    }
+    const int64_t n = g.size();
+    pos.push_back({want[w].dst, host.size()});
+    for (int64_t i = 0; i < n; ++i) host.push_back(g.offset(want[w].slot, i));
+  }
+}
+
+// Uploads the tables in one allocation and points the Offs at it.
+tc_status upload_tables(const std::vector<int64_t>& host, const std::vector<std::pair<tc::Offs*, size_t>>& pos,
+                        int64_t** dev) {
+  *dev = nullptr;
+  if (host.empty()) return TC_OK;
+  hipError_t e = hipMalloc((void**)dev, host.size() * sizeof(int64_t));
+  if (e != hipSuccess) return fail(TC_ERR_NOMEM, std::string("hipMalloc of offset tables: ") + hipGetErrorString(e));
+  e = hipMemcpy(*dev, host.data(), host.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(*dev);
+    *dev = nullptr;
+    return hip_fail(e, "hipMemcpy of offset tables");
+  }
+  for (auto& wp : pos) {
+    wp.first->tab = *dev + wp.second;
+    wp.first->stride = 0;
+  }
   return TC_OK;
 }
 
@@ -60,10 +116,156 @@ tc_status analyze_args(int ra, const int64_t* ea, const int64_t* sa, const int32
 
 struct tc_plan_s {
   tc::Analysis an;
+  tc::TensorDesc desc[3];  // A, B, C as given
+  tc_options opt{};
   int device = 0;
   int64_t* d_tables = nullptr;
   // per-group offsets of each kernel operand (A: M,K,L; B: N,K,L; C: M,N,L)
   tc::Offs aM{}, aK{}, aL{}, bN{}, bK{}, bL{}, cM{}, cN{}, cL{};
+};
+
+// A batch: items (layouts of its contractions) and the task list of the
+// current tile configuration live on the device; pointers and scalars go
+// through a pinned host buffer and a small device array at every execution.
+struct tc_batch_s {
+  int n = 0;
+  int device = 0;
+  int num_cus = 256;
+  int config = -1;
+  int use_graph = 1;
+  int64_t ntasks = 0;
+  std::vector<tc::BatchItem> items;
+  std::vector<tc_plan_info> analyses;
+  int64_t* d_tables = nullptr;
+  tc::BatchItem* d_items = nullptr;
+  tc::BatchTask* d_tasks = nullptr;
+  tc::BatchPtrs* h_ptrs = nullptr;
+  hipStream_t capture_stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool done_recorded = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* graph_ws = nullptr;
+
+  ~tc_batch_s() {
+    if (done_recorded) (void)hipEventSynchronize(done);
+    drop_graph();
+    if (done) (void)hipEventDestroy(done);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    if (h_ptrs) (void)hipHostFree(h_ptrs);
+    if (d_tasks) (void)hipFree(d_tasks);
+    if (d_items) (void)hipFree(d_items);
+    if (d_tables) (void)hipFree(d_tables);
+  }
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    graph_ws = nullptr;
+  }
+
+  size_t ptrs_bytes() const { return ((size_t)n * sizeof(tc::BatchPtrs) + 255) / 256 * 256; }
+  size_t workspace_bytes() const { return ptrs_bytes() + 256; }
+
+  // Tiles and task list for one tile configuration, longest tasks first.
+  tc_status set_config(int cfg) {
+    if (done_recorded) (void)hipEventSynchronize(done);
+    drop_graph();
+    const int BM = tc::kBatchTileBM[cfg], BN = tc::kBatchTileBN[cfg];
+    struct HT {
+      double cost;
+      tc::BatchTask t;
+    };
+    std::vector<HT> tasks;
+    for (int i = 0; i < n; ++i) {
+      tc::BatchItem& it = items[i];
+      if (it.kind == 0) {
+        it.tilesM = (it.g.M + BM - 1) / BM;
+        it.tilesN = (it.g.N + BN - 1) / BN;
+        const int64_t nt = it.tilesM * it.tilesN * it.g.L;
+        // cost of a tile: the larger of its FP64 MFMA time and its load time
+        const double flops = 2.0 * BM * BN * (double)it.g.K, bytes = 8.0 * (BM + BN) * (double)it.g.K + 8.0 * BM * BN;
+        const double cost = std::max(flops / 78.6e12, bytes / 8e12);
+        for (int64_t t = 0; t < nt; ++t) tasks.push_back({cost, tc::BatchTask{i, 0, t}});
+      } else {
+        const int64_t nt = (it.b.L + it.b.P - 1) / it.b.P;
+        const double bytes = 8.0 * it.b.P * (it.b.a.size + it.b.b.size + it.b.c.size);
+        const double cost = bytes / 8e12;
+        for (int64_t t = 0; t < nt; ++t) tasks.push_back({cost, tc::BatchTask{i, 0, t}});
+      }
+    }
+    std::stable_sort(tasks.begin(), tasks.end(), [](const HT& a, const HT& b) { return a.cost > b.cost; });
+    std::vector<tc::BatchTask> flat(tasks.size());
+    for (size_t i = 0; i < tasks.size(); ++i) flat[i] = tasks[i].t;
+    if (d_tasks) (void)hipFree(d_tasks);
+    d_tasks = nullptr;
+    ntasks = (int64_t)flat.size();
+    if (ntasks > 0) {
+      if (hipMalloc((void**)&d_tasks, flat.size() * sizeof(tc::BatchTask)) != hipSuccess)
+        return fail(TC_ERR_NOMEM, "batch task list");
+      if (hipMemcpy(d_tasks, flat.data(), flat.size() * sizeof(tc::BatchTask), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(TC_ERR_HIP, "upload of batch task list");
+    }
+    if (!d_items && hipMalloc((void**)&d_items, items.size() * sizeof(tc::BatchItem)) != hipSuccess)
+      return fail(TC_ERR_NOMEM, "batch items");
+    if (hipMemcpy(d_items, items.data(), items.size() * sizeof(tc::BatchItem), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(TC_ERR_HIP, "upload of batch items");
+    config = cfg;
+    return TC_OK;
+  }
+
+  hipError_t enqueue(void* ws, hipStream_t st) {
+    tc::BatchPtrs* d_ptrs = (tc::BatchPtrs*)ws;
+    unsigned long long* counter = (unsigned long long*)((char*)ws + ptrs_bytes());
+    hipError_t e = hipMemcpyAsync(d_ptrs, h_ptrs, sizeof(tc::BatchPtrs) * n, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    tc::BatchLaunch bl{d_items, d_ptrs, d_tasks, ntasks, counter, config, tc::kBatchSlabLdsDoubles, num_cus};
+    return tc::launch_batch(bl, st);
+  }
+
+  tc_status execute(const double* const* A, const double* const* B, double* const* C, const double* alpha,
+                    const double* beta, void* ws, size_t wsb, hipStream_t st, int graph_on) {
+    if (!A || !B || !C || !alpha || !beta) return fail(TC_ERR_INVALID_ARG, "null pointer array");
+    if (!ws || wsb < workspace_bytes())
+      return fail(TC_ERR_WORKSPACE, "batch workspace of " + std::to_string(wsb) + " bytes, needs " +
+                                        std::to_string(workspace_bytes()));
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != device)
+      return fail(TC_ERR_INVALID_ARG, "batch was created on another device");
+    for (int i = 0; i < n; ++i) {
+      if (analyses[i].M * analyses[i].N * analyses[i].L > 0 && !C[i])
+        return fail(TC_ERR_INVALID_ARG, "null C in batch entry " + std::to_string(i));
+    }
+    // the previous execution must have consumed the pinned staging buffer
+    if (done_recorded && hipEventSynchronize(done) != hipSuccess) return fail(TC_ERR_HIP, "batch event sync");
+    for (int i = 0; i < n; ++i) h_ptrs[i] = tc::BatchPtrs{A[i], B[i], C[i], alpha[i], beta[i]};
+    hipError_t e;
+    if (graph_on) {
+      if (!exec || graph_ws != ws) {
+        drop_graph();
+        e = hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t eq = enqueue(ws, capture_stream);
+        e = hipStreamEndCapture(capture_stream, &graph);
+        if (eq != hipSuccess) return hip_fail(eq, "batch capture");
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        graph_ws = ws;
+      }
+      e = hipGraphLaunch(exec, st);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    } else {
+      e = enqueue(ws, st);
+      if (e != hipSuccess) return hip_fail(e, "batch launch");
+    }
+    e = hipEventRecord(done, st);
+    if (e != hipSuccess) return hip_fail(e, "batch event record");
+    done_recorded = true;
+    return TC_OK;
+  }
 };
 
 extern "C" {
@@ -95,7 +297,7 @@ tc_status tc_plan_create(tc_plan_t* out, int ra, const int64_t* ea, const int64_
   *out = nullptr;
   tc_plan_s* p = new (std::nothrow) tc_plan_s();
   if (!p) return fail(TC_ERR_NOMEM, "host allocation failed");
-  tc_status s = analyze_args(ra, ea, sa, la, rb, eb, sb, lb, rc, ec, sc, lc, opt, &p->an);
+  tc_status s = analyze_args(ra, ea, sa, la, rb, eb, sb, lb, rc, ec, sc, lc, opt, &p->an, p->desc, &p->opt);
   if (s != TC_OK) {
     delete p;
     return s;
@@ -105,44 +307,14 @@ tc_status tc_plan_create(tc_plan_t* out, int ra, const int64_t* ea, const int64_
     delete p;
     return hip_fail(e, "hipGetDevice");
   }
-  // Offset tables: one per (group, operand) with more than one mode; a group
-  // of zero or one mode is affine and needs none.
-  const tc::Group* G = p->an.g;
-  struct Want {
-    int group, slot;
-    tc::Offs* dst;
-  } want[9] = {{tc::GM, tc::SA, &p->aM}, {tc::GK, tc::SA, &p->aK}, {tc::GL, tc::SA, &p->aL},
-               {tc::GN, tc::SB, &p->bN}, {tc::GK, tc::SB, &p->bK}, {tc::GL, tc::SB, &p->bL},
-               {tc::GM, tc::SC, &p->cM}, {tc::GN, tc::SC, &p->cN}, {tc::GL, tc::SC, &p->cL}};
   std::vector<int64_t> host;
-  std::vector<std::pair<int, size_t>> pos;  // (want index, start in host)
-  for (int w = 0; w < 9; ++w) {
-    const tc::Group& g = G[want[w].group];
-    if (g.n <= 1 || p->an.empty_out) {
-      want[w].dst->tab = nullptr;
-      want[w].dst->stride = g.n == 1 ? g.str[want[w].slot][0] : 0;
-      continue;
-    }
-    int64_t n = g.size();
-    pos.push_back({w, host.size()});
-    for (int64_t i = 0; i < n; ++i) host.push_back(g.offset(want[w].slot, i));
-  }
-  if (!host.empty()) {
-    e = hipMalloc((void**)&p->d_tables, host.size() * sizeof(int64_t));
-    if (e != hipSuccess) {
-      delete p;
-      return fail(TC_ERR_NOMEM, std::string("hipMalloc of offset tables: ") + hipGetErrorString(e));
-    }
-    e = hipMemcpy(p->d_tables, host.data(), host.size() * sizeof(int64_t), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipFree(p->d_tables);
-      delete p;
-      return hip_fail(e, "hipMemcpy of offset tables");
-    }
-    for (auto& wp : pos) {
-      want[wp.first].dst->tab = p->d_tables + wp.second;
-      want[wp.first].dst->stride = 0;
-    }
+  std::vector<std::pair<tc::Offs*, size_t>> pos;
+  build_tables(p->an, OffsTargets{&p->aM, &p->aK, &p->aL, &p->bN, &p->bK, &p->bL, &p->cM, &p->cN, &p->cL}, host,
+               pos);
+  s = upload_tables(host, pos, &p->d_tables);
+  if (s != TC_OK) {
+    delete p;
+    return s;
   }
   *out = p;
   return TC_OK;
@@ -257,6 +429,35 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
   gp.L = info.L;
   gp.alpha = alpha;
   gp.beta = beta;
+  if (an.kernel == tc::Analysis::KERNEL_BATCHED) {
+    tc::BatchedParams bp{};
+    bp.A = KA;
+    bp.B = KB;
+    bp.C = C;
+    bp.aL = plan->aL;
+    bp.bL = plan->bL;
+    bp.cL = plan->cL;
+    tc::SlabDesc* d[3] = {&bp.a, &bp.b, &bp.c};
+    for (int slot = 0; slot < 3; ++slot) {
+      d[slot]->n = an.slab_n[slot];
+      d[slot]->size = an.slab_size[slot];
+      d[slot]->batch_fast = an.slab_batch_fast[slot];
+      for (int i = 0; i < an.slab_n[slot]; ++i) {
+        d[slot]->ext[i] = an.slab_ext[slot][i];
+        d[slot]->gstr[i] = an.slab_gstr[slot][i];
+        d[slot]->lstr[i] = an.slab_lstr[slot][i];
+      }
+    }
+    bp.M = (int)info.M;
+    bp.N = (int)info.N;
+    bp.K = (int)info.K;
+    bp.P = an.batched_P;
+    bp.L = info.L;
+    bp.alpha = alpha;
+    bp.beta = beta;
+    e = tc::launch_batched_small(bp, s);
+    return e == hipSuccess ? TC_OK : hip_fail(e, "batched launch");
+  }
   if (an.kernel == tc::Analysis::KERNEL_LANES_OUT) {
     e = tc::launch_lanes_over_outputs(gp, an.n_fastest, s);
     return e == hipSuccess ? TC_OK : hip_fail(e, "lanes-over-outputs launch");
@@ -314,19 +515,211 @@ tc_status tc_permute(int rank, const int64_t* ext, const int64_t* str_x, const i
   return e == hipSuccess ? TC_OK : hip_fail(e, "permute launch");
 }
 
-tc_status tc_batch_create(tc_batch_t* out, int, const tc_plan_t*) {
-  if (out) *out = nullptr;
-  return fail(TC_ERR_UNSUPPORTED, "batches are not built in");
+tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
+  if (!out) return fail(TC_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (n < 1 || !plans) return fail(TC_ERR_INVALID_ARG, "a batch needs n >= 1 plans");
+  tc_batch_s* b = new (std::nothrow) tc_batch_s();
+  if (!b) return fail(TC_ERR_NOMEM, "host allocation failed");
+  b->n = n;
+  hipError_t e = hipGetDevice(&b->device);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "hipGetDevice");
+  }
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, b->device);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "hipGetDeviceProperties");
+  }
+  b->num_cus = prop.multiProcessorCount;
+  b->items.resize(n);
+  b->analyses.resize(n);
+  std::vector<int64_t> host;
+  std::vector<std::pair<tc::Offs*, size_t>> pos;
+  for (int i = 0; i < n; ++i) {
+    const tc_plan_s* p = plans[i];
+    if (!p) {
+      delete b;
+      return fail(TC_ERR_INVALID_ARG, "null plan in batch");
+    }
+    if (p->opt.precision != TC_PREC_F64) {
+      delete b;
+      return fail(TC_ERR_UNSUPPORTED, "batches run FP64 plans only");
+    }
+    if (p->device != b->device) {
+      delete b;
+      return fail(TC_ERR_INVALID_ARG, "plans of a batch must share the current device");
+    }
+    // Re-plan for the batch's two engines: batch-dominated contractions keep
+    // the slab engine, everything else runs as direct GEMM tiles (a batch has
+    // no per-contraction copy or memory-bound kernels).
+    tc_options o = p->opt;
+    o.recipe = TC_RECIPE_AUTO;
+    tc::Analysis an;
+    std::string err;
+    tc_status s = tc::analyze(p->desc[0], p->desc[1], p->desc[2], o, &an, &err);
+    if (s == TC_OK && an.kernel != tc::Analysis::KERNEL_BATCHED) {
+      o.recipe = TC_RECIPE_GEMM;
+      s = tc::analyze(p->desc[0], p->desc[1], p->desc[2], o, &an, &err);
+    }
+    if (s != TC_OK) {
+      delete b;
+      return fail(s, err);
+    }
+    tc::BatchItem& it = b->items[i];
+    std::memset(&it, 0, sizeof(it));
+    it.swapped = an.info.swapped;
+    if (an.kernel == tc::Analysis::KERNEL_BATCHED) {
+      it.kind = 1;
+      build_tables(an, OffsTargets{&it.g.aM, &it.g.aK, &it.b.aL, &it.g.bN, &it.g.bK, &it.b.bL, &it.g.cM, &it.g.cN,
+                                   &it.b.cL},
+                   host, pos);
+      tc::SlabDesc* d[3] = {&it.b.a, &it.b.b, &it.b.c};
+      for (int slot = 0; slot < 3; ++slot) {
+        d[slot]->n = an.slab_n[slot];
+        d[slot]->size = an.slab_size[slot];
+        d[slot]->batch_fast = an.slab_batch_fast[slot];
+        for (int q = 0; q < an.slab_n[slot]; ++q) {
+          d[slot]->ext[q] = an.slab_ext[slot][q];
+          d[slot]->gstr[q] = an.slab_gstr[slot][q];
+          d[slot]->lstr[q] = an.slab_lstr[slot][q];
+        }
+      }
+      const int per = an.slab_size[0] + an.slab_size[1] + an.slab_size[2];
+      int P = tc::kBatchSlabLdsDoubles / per;
+      if (P > 64) P = 64;
+      if (P < 1) {
+        delete b;
+        return fail(TC_ERR_UNSUPPORTED, "batch slab too large");
+      }
+      it.b.P = P;
+      it.b.M = (int)an.info.M;
+      it.b.N = (int)an.info.N;
+      it.b.K = (int)an.info.K;
+      it.b.L = an.info.L;
+    } else {
+      it.kind = 0;
+      build_tables(an, OffsTargets{&it.g.aM, &it.g.aK, &it.g.aL, &it.g.bN, &it.g.bK, &it.g.bL, &it.g.cM, &it.g.cN,
+                                   &it.g.cL},
+                   host, pos);
+      it.akf = an.a_kfast ? 1 : 0;
+      it.bkf = an.b_kfast ? 1 : 0;
+      it.g.M = an.empty_out ? 0 : an.info.M;
+      it.g.N = an.empty_out ? 0 : an.info.N;
+      it.g.K = an.info.K;
+      it.g.L = an.empty_out ? 0 : an.info.L;
+    }
+    b->analyses[i] = an.info;
+  }
+  // table pointers live inside the items: patch them after the upload
+  tc_status s = upload_tables(host, pos, &b->d_tables);
+  if (s != TC_OK) {
+    delete b;
+    return s;
+  }
+  e = hipHostMalloc((void**)&b->h_ptrs, sizeof(tc::BatchPtrs) * n, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(TC_ERR_NOMEM, "pinned host staging of batch pointers");
+  }
+  e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "batch stream/event");
+  }
+  s = b->set_config(0);
+  if (s != TC_OK) {
+    delete b;
+    return s;
+  }
+  *out = b;
+  return TC_OK;
 }
-tc_status tc_batch_workspace(tc_batch_t, size_t* bytes) {
-  if (bytes) *bytes = 0;
-  return fail(TC_ERR_UNSUPPORTED, "batches are not built in");
+
+tc_status tc_batch_workspace(tc_batch_t batch, size_t* bytes) {
+  if (!batch || !bytes) return fail(TC_ERR_INVALID_ARG, "null batch or bytes");
+  *bytes = batch->workspace_bytes();
+  return TC_OK;
 }
-tc_status tc_batch_execute(tc_batch_t, const double* const*, const double* const*, double* const*, const double*,
-                           const double*, void*, size_t, void*) {
-  return fail(TC_ERR_UNSUPPORTED, "batches are not built in");
+
+tc_status tc_batch_execute(tc_batch_t batch, const double* const* A, const double* const* B, double* const* C,
+                           const double* alpha, const double* beta, void* workspace, size_t workspace_bytes,
+                           void* stream) {
+  if (!batch) return fail(TC_ERR_INVALID_ARG, "batch is null");
+  return batch->execute(A, B, C, alpha, beta, workspace, workspace_bytes, (hipStream_t)stream, batch->use_graph);
 }
-tc_status tc_batch_destroy(tc_batch_t) { return TC_OK; }
+
+tc_status tc_batch_set_options(tc_batch_t batch, int tile_config, int use_graph) {
+  if (!batch) return fail(TC_ERR_INVALID_ARG, "batch is null");
+  if (tile_config < -1 || tile_config >= tc::kNumBatchTiles)
+    return fail(TC_ERR_INVALID_ARG, "batch tile configuration out of range");
+  if (tile_config >= 0 && tile_config != batch->config) {
+    tc_status s = batch->set_config(tile_config);
+    if (s != TC_OK) return s;
+  }
+  batch->use_graph = use_graph ? 1 : 0;
+  return TC_OK;
+}
+
+tc_status tc_batch_query(tc_batch_t batch, int64_t* ntasks, int* tile_config, int* use_graph) {
+  if (!batch) return fail(TC_ERR_INVALID_ARG, "batch is null");
+  if (ntasks) *ntasks = batch->ntasks;
+  if (tile_config) *tile_config = batch->config;
+  if (use_graph) *use_graph = batch->use_graph;
+  return TC_OK;
+}
+
+tc_status tc_batch_autotune(tc_batch_t batch, const double* const* A, const double* const* B, double* const* C,
+                            const double* alpha, const double* beta, void* workspace, size_t workspace_bytes,
+                            void* stream, int* best_config, double* best_ms) {
+  if (!batch) return fail(TC_ERR_INVALID_ARG, "batch is null");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(TC_ERR_HIP, "event create");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(TC_ERR_HIP, "event create");
+  }
+  int best = -1;
+  float best_t = 0.f;
+  tc_status s = TC_OK;
+  for (int cfg = 0; cfg < tc::kNumBatchTiles && s == TC_OK; ++cfg) {
+    s = batch->set_config(cfg);
+    if (s != TC_OK) break;
+    // one untimed run, then the median of three timed ones
+    s = batch->execute(A, B, C, alpha, beta, workspace, workspace_bytes, st, 0);
+    float t[3];
+    for (int r = 0; r < 3 && s == TC_OK; ++r) {
+      (void)hipEventRecord(e0, st);
+      s = batch->execute(A, B, C, alpha, beta, workspace, workspace_bytes, st, 0);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) s = fail(TC_ERR_HIP, "event sync");
+      (void)hipEventElapsedTime(&t[r], e0, e1);
+    }
+    if (s != TC_OK) break;
+    std::sort(t, t + 3);
+    if (best < 0 || t[1] < best_t) {
+      best = cfg;
+      best_t = t[1];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != TC_OK) return s;
+  s = batch->set_config(best);
+  if (s != TC_OK) return s;
+  if (best_config) *best_config = best;
+  if (best_ms) *best_ms = best_t;
+  return TC_OK;
+}
+
+tc_status tc_batch_destroy(tc_batch_t batch) {
+  delete batch;
+  return TC_OK;
+}
 
 const char* tc_status_string(tc_status s) {
   switch (s) {

@@ -123,6 +123,71 @@ inline constexpr SplitTile split_tile(bool fp8, int slices) {
 }
 hipError_t launch_split_contraction(const SplitParams& sp, hipStream_t s);
 
+// Batch-dominated contractions: per-point slabs staged through LDS.
+struct SlabDesc {
+  int n;                 // modes of the operand inside one slab
+  int size;              // entries per slab
+  int batch_fast;        // the batch index varies fastest in memory
+  int ext[kMaxRank];     // extents, sorted by global stride
+  int64_t gstr[kMaxRank];  // global strides
+  int lstr[kMaxRank];    // strides in the canonical LDS slab
+};
+struct BatchedParams {
+  const double* A;
+  const double* B;
+  double* C;
+  Offs aL, bL, cL;
+  SlabDesc a, b, c;
+  int M, N, K;           // per-point group sizes
+  int P;                 // batch indices per workgroup
+  int64_t L;
+  double alpha, beta;
+};
+constexpr int kBatchedLdsDoubles = 8192;  // 64 KB of LDS per workgroup
+hipError_t launch_batched_small(const BatchedParams& bp, hipStream_t s);
+
+// Persistent batches.  Tile configurations of the batch kernel (id, rows,
+// columns, contracted depth; 2 x 2 wavefronts each).
+#define TC_BATCH_TILES(X) \
+  X(0, 64, 64, 16)        \
+  X(1, 32, 32, 16)        \
+  X(2, 128, 64, 16)       \
+  X(3, 64, 128, 16)
+constexpr int kNumBatchTiles = 4;
+constexpr int kBatchTileBM[kNumBatchTiles] = {64, 32, 128, 64};
+constexpr int kBatchTileBN[kNumBatchTiles] = {64, 32, 64, 128};
+constexpr int kBatchSlabLdsDoubles = 4096;  // slab LDS of batch tasks (32 KB)
+struct BatchItem {       // one contraction of a batch (layout only)
+  GettParams g;          // kind 0: GEMM tiles
+  BatchedParams b;       // kind 1: slabs of batch indices
+  int kind;
+  int akf, bkf, swapped;
+  int64_t tilesM, tilesN;
+};
+struct BatchPtrs {       // per execution
+  const double* A;
+  const double* B;
+  double* C;
+  double alpha, beta;
+};
+struct BatchTask {
+  int item;
+  int pad;
+  int64_t idx;           // tile index (kind 0) or slab index (kind 1)
+};
+struct BatchLaunch {
+  const BatchItem* items;
+  const BatchPtrs* ptrs;
+  const BatchTask* tasks;
+  int64_t ntasks;
+  unsigned long long* counter;
+  int config;
+  int slab_lds_doubles;
+  int num_cus;
+};
+size_t batch_lds_bytes(int config, int slab_lds_doubles);
+hipError_t launch_batch(const BatchLaunch& bl, hipStream_t s);
+
 // Y[sum idx_i sy_i] = X[sum idx_i sx_i] over all multi-indices.
 struct PermuteParams {
   const double* X;

@@ -20,6 +20,9 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <tuple>
+#include <vector>
+#include <climits>
 
 namespace tc {
 namespace {
@@ -136,6 +139,55 @@ int pick_tile(int64_t M, int64_t N, int64_t L) {
   if (tiles(128, 128) >= 256) return 9;
   if (tiles(64, 64) >= 256) return 1;
   return 8;
+}
+
+// A batch-dominated contraction: at least 64 batch indices and per-point
+// slabs of A, B and C small enough for several points per workgroup.
+bool batched_fits(const tc_plan_info& info, const Group* G) {
+  if (G[GL].n == 0 || info.L < 64) return false;
+  if (info.M > 1024 || info.N > 1024 || info.K > 1024) return false;
+  const int64_t per = info.M * info.K + info.N * info.K + info.M * info.N;
+  return per * 4 <= kBatchedLdsDoubles;
+}
+
+// Slab descriptors: each operand's non-batch modes sorted by global stride,
+// with strides into the canonical LDS slab ([m][k] for A, [n][k] for B,
+// [m][n] for C; the group's own mode order decodes column-major).
+void build_slabs(Analysis& an) {
+  const Group* G = an.g;
+  const int64_t M = an.info.M, N = an.info.N, K = an.info.K;
+  struct Use {
+    int group;
+    int64_t lweight;  // LDS stride of the group's linear index
+  };
+  const Use uses[3][2] = {{{GM, K}, {GK, 1}}, {{GN, K}, {GK, 1}}, {{GM, N}, {GN, 1}}};
+  for (int slot = 0; slot < 3; ++slot) {
+    std::vector<std::tuple<int64_t, int, int>> modes;  // (gstride, ext, lstride)
+    for (const Use& u : uses[slot]) {
+      const Group& g = G[u.group];
+      int64_t w = u.lweight;
+      for (int i = 0; i < g.n; ++i) {
+        modes.emplace_back(g.str[slot][i], (int)g.ext[i], (int)w);
+        w *= g.ext[i];
+      }
+    }
+    std::sort(modes.begin(), modes.end());
+    an.slab_n[slot] = (int)modes.size();
+    int size = 1;
+    for (size_t i = 0; i < modes.size(); ++i) {
+      an.slab_gstr[slot][i] = std::get<0>(modes[i]);
+      an.slab_ext[slot][i] = std::get<1>(modes[i]);
+      an.slab_lstr[slot][i] = std::get<2>(modes[i]);
+      size *= std::get<1>(modes[i]);
+    }
+    an.slab_size[slot] = size;
+    const int64_t min_slab = modes.empty() ? INT64_MAX : std::get<0>(modes[0]);
+    an.slab_batch_fast[slot] = G[GL].n > 0 && G[GL].str[slot][0] < min_slab ? 1 : 0;
+  }
+  const int per = an.slab_size[0] + an.slab_size[1] + an.slab_size[2];
+  int P = kBatchedLdsDoubles / per;
+  an.batched_P = P > 64 ? 64 : P;
+  (void)M;
 }
 
 }  // namespace
@@ -393,6 +445,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
       return TC_ERR_UNSUPPORTED;
     }
     info.recipe = TC_RECIPE_GEMM;
+    an.kernel = Analysis::KERNEL_SPLIT;
     info.split_slices = S;
     an.slices = S;
     const SplitTile t = split_tile(fp8, S);
@@ -417,6 +470,11 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     const int64_t needB = row_max_segments(info.N, info.K) * info.N;
     off = al(off + (size_t)(needA > needB ? needA : needB) * sizeof(double));
     info.workspace_bytes = off;
+  } else if (opt.recipe == TC_RECIPE_AUTO && batched_fits(info, G)) {
+    // Many tiny contractions sharing one layout (the batch group dominates):
+    // per-point slabs through LDS, all batch indices in one launch.
+    an.kernel = Analysis::KERNEL_BATCHED;
+    build_slabs(an);
   } else if (recipe == TC_RECIPE_GEMM || recipe == TC_RECIPE_COPY_GEMM) {
     info.tile_id = opt.tile_id >= 0 ? opt.tile_id : pick_tile(info.M, info.N, info.L);
   } else {
@@ -448,6 +506,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
       }
     }
   }
+  info.kernel = an.kernel;
   *out = an;
   return TC_OK;
 }

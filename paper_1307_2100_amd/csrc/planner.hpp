@@ -58,7 +58,7 @@ struct Analysis {
   bool a_kfast = false;     // kernel A's stride-1 mode leads the contracted group
   bool b_kfast = false;     // kernel B's stride-1 mode leads the contracted group
   // GEMV / DOT / GER recipes: which memory-bound kernel runs them
-  enum { KERNEL_GETT = 0, KERNEL_LANES_OUT = 1, KERNEL_LANES_K = 2 };
+  enum { KERNEL_GETT = 0, KERNEL_LANES_OUT = 1, KERNEL_LANES_K = 2, KERNEL_BATCHED = 3, KERNEL_SPLIT = 4 };
   int kernel = KERNEL_GETT;
   bool n_fastest = false;   // lanes-over-outputs: consecutive lanes along n
   int64_t seg = 1;          // lanes-over-k: contracted segments per output
@@ -70,6 +70,12 @@ struct Analysis {
   int64_t Mp = 0, Np = 0, Kp = 0;
   size_t planesA_off = 0, planesB_off = 0, sigA_off = 0, sigB_off = 0, part_off = 0;
   int64_t elems[3] = {};    // entries of kernel A, kernel B, C (products of extents)
+  // batched small contractions: slab descriptors (without pointers)
+  int batched_P = 0;
+  int slab_n[3] = {}, slab_size[3] = {}, slab_batch_fast[3] = {};
+  int slab_ext[3][TC_MAX_RANK] = {};
+  int64_t slab_gstr[3][TC_MAX_RANK] = {};
+  int slab_lstr[3][TC_MAX_RANK] = {};
   // COPY_GEMM: the copied operand (kernel slot) and its modes before and after
   // the copy, in the copied tensor's own storage order.
   int copy_slot = -1;
