@@ -107,6 +107,7 @@ typedef struct {
   int split_slices;            /* digits per input (split precision), 0 otherwise */
   int kernel;                  /* kernel family: 0 MFMA GEMM, 1 lanes over outputs, 2 lanes over k,
                                   3 batched small slabs, 4 split-precision digits */
+  int k_split;                 /* MFMA GEMM: segments of the contracted range (1 = none) */
 } tc_plan_info;
 
 /* Fills *opt with the defaults listed in tc_options. */
@@ -172,8 +173,9 @@ tc_status tc_batch_workspace(tc_batch_t batch, size_t* bytes);
 tc_status tc_batch_execute(tc_batch_t batch, const double* const* A, const double* const* B,
                            double* const* C, const double* alpha, const double* beta,
                            void* workspace, size_t workspace_bytes, void* stream);
-/* tile_config: -1 keeps the current one, else 0..3 (64x64, 32x32, 128x64,
- * 64x128 GEMM tiles); use_graph: 0 launches eagerly, 1 replays a hipGraph. */
+/* tile_config: -1 keeps the current one, else 0..5 (GEMM tiles rows x columns
+ * x depth: 64x64x16, 32x32x16, 32x32x64, 64x64x32, 32x32x128, 64x64x64);
+ * use_graph: 0 launches eagerly, 1 replays a hipGraph. */
 tc_status tc_batch_set_options(tc_batch_t batch, int tile_config, int use_graph);
 tc_status tc_batch_query(tc_batch_t batch, int64_t* ntasks, int* tile_config, int* use_graph);
 /* Autotuner: times every tile configuration on the given buffers (C is

@@ -44,7 +44,7 @@ RECIPES = {"auto": 0, "gemm": 1, "copy_gemm": 2, "gemv": 3, "ger": 4, "dot": 5}
 RECIPE_NAMES = {v: k for k, v in RECIPES.items()}
 KERNEL_NAMES = {0: "mfma_gemm", 1: "lanes_over_outputs", 2: "lanes_over_k", 3: "batched_small", 4: "split_digits"}
 # GEMM tile configurations compiled into libtc (ids 0 .. NUM_TILES-1)
-NUM_TILES = 14
+NUM_TILES = 18
 # tc_picker
 TC_PICKER_RULES, TC_PICKER_MLP, TC_PICKER_TUNED = 0, 1, 2
 
@@ -62,7 +62,8 @@ class tc_plan_info(ctypes.Structure):
                 ("nM", ctypes.c_int), ("nN", ctypes.c_int), ("nK", ctypes.c_int), ("nL", ctypes.c_int),
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t), ("precision", ctypes.c_int),
-                ("split_slices", ctypes.c_int), ("kernel", ctypes.c_int)]
+                ("split_slices", ctypes.c_int), ("kernel", ctypes.c_int),
+                ("k_split", ctypes.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

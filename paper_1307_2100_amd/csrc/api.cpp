@@ -81,6 +81,7 @@ void build_tables(const tc::Analysis& an, const OffsTargets& t, std::vector<int6
                {tc::GM, tc::SC, t.cM}, {tc::GN, tc::SC, t.cN}, {tc::GL, tc::SC, t.cL}};
   for (int w = 0; w < 9; ++w) {
     const tc::Group& g = G[want[w].group];
+    *want[w].dst = tc::Offs{};
     if (g.n <= 1 || an.empty_out) {
       want[w].dst->tab = nullptr;
       want[w].dst->stride = g.n == 1 ? g.str[want[w].slot][0] : 0;
@@ -139,6 +140,8 @@ struct tc_batch_s {
   int64_t* d_tables = nullptr;
   tc::BatchItem* d_items = nullptr;
   tc::BatchTask* d_tasks = nullptr;
+  int64_t* d_chunks = nullptr;
+  int64_t nchunks = 0;
   tc::BatchPtrs* h_ptrs = nullptr;
   hipStream_t capture_stream = nullptr;
   hipEvent_t done = nullptr;
@@ -154,6 +157,7 @@ struct tc_batch_s {
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
     if (h_ptrs) (void)hipHostFree(h_ptrs);
     if (d_tasks) (void)hipFree(d_tasks);
+    if (d_chunks) (void)hipFree(d_chunks);
     if (d_items) (void)hipFree(d_items);
     if (d_tables) (void)hipFree(d_tables);
   }
@@ -166,8 +170,30 @@ struct tc_batch_s {
     graph_ws = nullptr;
   }
 
+  // workspace: [pointers][task counter][tile counters][partial tiles]
+  int64_t n_cnt = 0;      // split tiles of the current configuration
+  int64_t n_parts = 0;    // partial tiles of the current configuration
+  size_t max_ws = 0;      // largest workspace over all configurations
   size_t ptrs_bytes() const { return ((size_t)n * sizeof(tc::BatchPtrs) + 255) / 256 * 256; }
-  size_t workspace_bytes() const { return ptrs_bytes() + 256; }
+  size_t cnt_offset() const { return ptrs_bytes() + 256; }
+  size_t parts_offset(int64_t ncnt) const { return cnt_offset() + ((size_t)ncnt * 4 + 255) / 256 * 256; }
+  size_t workspace_for(int64_t ncnt, int64_t nparts, int cfg) const {
+    return parts_offset(ncnt) + (size_t)nparts * tc::kBatchTileBM[cfg] * tc::kBatchTileBN[cfg] * sizeof(double);
+  }
+  size_t workspace_bytes() const { return max_ws; }
+
+  // Split-K for a GEMM item with `tiles` output tiles: long contracted ranges
+  // are cut into segments of at least 1024 indices so that no task dominates.
+  static void item_split(int64_t tiles, int64_t K, int* S, int64_t* len) {
+    *S = 1;
+    *len = K;
+    if (K <= 2048 || tiles >= 256) return;
+    int64_t l = (K + 255) / 256;
+    if (l < 1024) l = 1024;
+    l = (l + 15) / 16 * 16;
+    *S = (int)((K + l - 1) / l);
+    *len = l;
+  }
 
   // Tiles and task list for one tile configuration, longest tasks first.
   tc_status set_config(int cfg) {
@@ -179,16 +205,31 @@ struct tc_batch_s {
       tc::BatchTask t;
     };
     std::vector<HT> tasks;
+    n_cnt = 0;
+    n_parts = 0;
     for (int i = 0; i < n; ++i) {
       tc::BatchItem& it = items[i];
       if (it.kind == 0) {
         it.tilesM = (it.g.M + BM - 1) / BM;
         it.tilesN = (it.g.N + BN - 1) / BN;
         const int64_t nt = it.tilesM * it.tilesN * it.g.L;
-        // cost of a tile: the larger of its FP64 MFMA time and its load time
-        const double flops = 2.0 * BM * BN * (double)it.g.K, bytes = 8.0 * (BM + BN) * (double)it.g.K + 8.0 * BM * BN;
+        int S;
+        int64_t len;
+        item_split(nt, it.g.K, &S, &len);
+        it.ksplit = S;
+        it.seg_len = len;
+        it.part_off = S > 1 ? n_parts : 0;
+        it.cnt_off = S > 1 ? n_cnt : 0;
+        if (S > 1) {
+          n_parts += nt * S;
+          n_cnt += nt;
+        }
+        // cost of a task: the larger of its FP64 MFMA time and its load time
+        const double k = (double)(S > 1 ? len : it.g.K);
+        const double flops = 2.0 * BM * BN * k, bytes = 8.0 * (BM + BN) * k + 8.0 * BM * BN;
         const double cost = std::max(flops / 78.6e12, bytes / 8e12);
-        for (int64_t t = 0; t < nt; ++t) tasks.push_back({cost, tc::BatchTask{i, 0, t}});
+        for (int64_t t = 0; t < nt; ++t)
+          for (int sg = 0; sg < S; ++sg) tasks.push_back({cost, tc::BatchTask{i, sg, t}});
       } else {
         const int64_t nt = (it.b.L + it.b.P - 1) / it.b.P;
         const double bytes = 8.0 * it.b.P * (it.b.a.size + it.b.b.size + it.b.c.size);
@@ -198,7 +239,30 @@ struct tc_batch_s {
     }
     std::stable_sort(tasks.begin(), tasks.end(), [](const HT& a, const HT& b) { return a.cost > b.cost; });
     std::vector<tc::BatchTask> flat(tasks.size());
-    for (size_t i = 0; i < tasks.size(); ++i) flat[i] = tasks[i].t;
+    double total = 0.0;
+    for (size_t i = 0; i < tasks.size(); ++i) {
+      flat[i] = tasks[i].t;
+      total += tasks[i].cost;
+    }
+    // chunks of about total / (16 per CU) cost: the costly tasks at the front
+    // get chunks of their own, the many cheap ones share
+    std::vector<int64_t> bounds{0};
+    const double target = total / (16.0 * num_cus);
+    double acc = 0.0;
+    for (size_t i = 0; i < tasks.size(); ++i) {
+      acc += tasks[i].cost;
+      if (acc >= target || i + 1 == tasks.size()) {
+        bounds.push_back((int64_t)i + 1);
+        acc = 0.0;
+      }
+    }
+    nchunks = (int64_t)bounds.size() - 1;
+    if (d_chunks) (void)hipFree(d_chunks);
+    d_chunks = nullptr;
+    if (hipMalloc((void**)&d_chunks, bounds.size() * sizeof(int64_t)) != hipSuccess)
+      return fail(TC_ERR_NOMEM, "batch chunk list");
+    if (hipMemcpy(d_chunks, bounds.data(), bounds.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(TC_ERR_HIP, "upload of batch chunk list");
     if (d_tasks) (void)hipFree(d_tasks);
     d_tasks = nullptr;
     ntasks = (int64_t)flat.size();
@@ -219,16 +283,19 @@ struct tc_batch_s {
   hipError_t enqueue(void* ws, hipStream_t st) {
     tc::BatchPtrs* d_ptrs = (tc::BatchPtrs*)ws;
     unsigned long long* counter = (unsigned long long*)((char*)ws + ptrs_bytes());
+    unsigned* cnt = (unsigned*)((char*)ws + cnt_offset());
+    double* parts = (double*)((char*)ws + parts_offset(n_cnt));
     hipError_t e = hipMemcpyAsync(d_ptrs, h_ptrs, sizeof(tc::BatchPtrs) * n, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
-    tc::BatchLaunch bl{d_items, d_ptrs, d_tasks, ntasks, counter, config, tc::kBatchSlabLdsDoubles, num_cus};
+    tc::BatchLaunch bl{d_items, d_ptrs, d_tasks, ntasks, d_chunks, nchunks, counter, parts, cnt, n_cnt, config,
+                       tc::kBatchSlabLdsDoubles, num_cus};
     return tc::launch_batch(bl, st);
   }
 
   tc_status execute(const double* const* A, const double* const* B, double* const* C, const double* alpha,
                     const double* beta, void* ws, size_t wsb, hipStream_t st, int graph_on) {
     if (!A || !B || !C || !alpha || !beta) return fail(TC_ERR_INVALID_ARG, "null pointer array");
-    if (!ws || wsb < workspace_bytes())
+    if (!ws || wsb < workspace_for(n_cnt, n_parts, config))
       return fail(TC_ERR_WORKSPACE, "batch workspace of " + std::to_string(wsb) + " bytes, needs " +
                                         std::to_string(workspace_bytes()));
     int dev = -1;
@@ -441,9 +508,10 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
     for (int slot = 0; slot < 3; ++slot) {
       d[slot]->n = an.slab_n[slot];
       d[slot]->size = an.slab_size[slot];
+      d[slot]->size_div = tc::make_fastdiv((uint32_t)an.slab_size[slot]);
       d[slot]->batch_fast = an.slab_batch_fast[slot];
       for (int i = 0; i < an.slab_n[slot]; ++i) {
-        d[slot]->ext[i] = an.slab_ext[slot][i];
+        d[slot]->div[i] = tc::make_fastdiv((uint32_t)an.slab_ext[slot][i]);
         d[slot]->gstr[i] = an.slab_gstr[slot][i];
         d[slot]->lstr[i] = an.slab_lstr[slot][i];
       }
@@ -452,6 +520,9 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
     bp.N = (int)info.N;
     bp.K = (int)info.K;
     bp.P = an.batched_P;
+    bp.P_div = tc::make_fastdiv((uint32_t)bp.P);
+    bp.N_div = tc::make_fastdiv((uint32_t)bp.N);
+    bp.sC_div = tc::make_fastdiv((uint32_t)bp.c.size);
     bp.L = info.L;
     bp.alpha = alpha;
     bp.beta = beta;
@@ -468,7 +539,8 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
     return e == hipSuccess ? TC_OK : hip_fail(e, "lanes-over-k launch");
   }
   int tile = info.tile_id >= 0 ? info.tile_id : 1;
-  e = tc::launch_gett_f64(gp, tile, an.a_kfast, an.b_kfast, s);
+  double* parts = info.k_split > 1 ? (double*)((char*)workspace + an.part_offset) : nullptr;
+  e = tc::launch_gett_f64(gp, tile, an.a_kfast, an.b_kfast, info.k_split, an.seg_len, parts, s);
   if (e != hipSuccess) return hip_fail(e, "gett launch");
   return TC_OK;
 }
@@ -580,9 +652,10 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
       for (int slot = 0; slot < 3; ++slot) {
         d[slot]->n = an.slab_n[slot];
         d[slot]->size = an.slab_size[slot];
+        d[slot]->size_div = tc::make_fastdiv((uint32_t)an.slab_size[slot]);
         d[slot]->batch_fast = an.slab_batch_fast[slot];
         for (int q = 0; q < an.slab_n[slot]; ++q) {
-          d[slot]->ext[q] = an.slab_ext[slot][q];
+          d[slot]->div[q] = tc::make_fastdiv((uint32_t)an.slab_ext[slot][q]);
           d[slot]->gstr[q] = an.slab_gstr[slot][q];
           d[slot]->lstr[q] = an.slab_lstr[slot][q];
         }
@@ -599,6 +672,9 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
       it.b.N = (int)an.info.N;
       it.b.K = (int)an.info.K;
       it.b.L = an.info.L;
+      it.b.P_div = tc::make_fastdiv((uint32_t)P);
+      it.b.N_div = tc::make_fastdiv((uint32_t)it.b.N);
+      it.b.sC_div = tc::make_fastdiv((uint32_t)it.b.c.size);
     } else {
       it.kind = 0;
       build_tables(an, OffsTargets{&it.g.aM, &it.g.aK, &it.g.aL, &it.g.bN, &it.g.bK, &it.g.bL, &it.g.cM, &it.g.cN,
@@ -630,10 +706,14 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
     delete b;
     return hip_fail(e, "batch stream/event");
   }
-  s = b->set_config(0);
-  if (s != TC_OK) {
-    delete b;
-    return s;
+  // the workspace must serve every tile configuration (the autotuner switches)
+  for (int cfg = tc::kNumBatchTiles - 1; cfg >= 0; --cfg) {
+    s = b->set_config(cfg);
+    if (s != TC_OK) {
+      delete b;
+      return s;
+    }
+    b->max_ws = std::max(b->max_ws, b->workspace_for(b->n_cnt, b->n_parts, cfg));
   }
   *out = b;
   return TC_OK;

@@ -8,13 +8,13 @@ namespace tc {
 
 // Decode linear index r of a slab over the operand's modes (sorted by global
 // stride): returns the global offset inside the slab and the LDS offset.
-__device__ inline void slab_decode(const SlabDesc& d, int r, int64_t* g, int* s) {
+__device__ inline void slab_decode(const SlabDesc& d, uint32_t r, int64_t* g, int* s) {
   int64_t go = 0;
   int so = 0;
-#pragma unroll 4
   for (int i = 0; i < d.n; ++i) {
-    const int v = r % d.ext[i];
-    r /= d.ext[i];
+    const uint32_t q = fdiv(r, d.div[i]);
+    const int v = (int)(r - q * d.div[i].d);
+    r = q;
     go += (int64_t)v * d.gstr[i];
     so += v * d.lstr[i];
   }
@@ -22,26 +22,42 @@ __device__ inline void slab_decode(const SlabDesc& d, int r, int64_t* g, int* s)
   *s = so;
 }
 
-// Copy the slabs of P batch indices (starting at l0, at most L - l0 of them)
-// of one operand into LDS (slab size `size` doubles per point).
+// Copy the slabs of np <= P batch indices starting at l0 of one operand into
+// LDS (slab size d.size doubles per point).  Each thread issues 8
+// independent loads before storing any, so that enough loads are in flight
+// to cover the memory latency.
 __device__ inline void slab_load(const double* __restrict__ X, const Offs& xl, const SlabDesc& d, int64_t l0,
-                                 int np, int P, double* __restrict__ lds, int tid, int nt) {
-  const int total = np * d.size;
-  for (int e = tid; e < total; e += nt) {
-    int p, r;
-    if (d.batch_fast) {
-      p = e % np;
-      r = e / np;
-    } else {
-      p = e / d.size;
-      r = e % d.size;
+                                 int np, int P, const FastDiv& P_div, double* __restrict__ lds, int tid, int nt) {
+  constexpr int U = 8;
+  const int total = P * d.size;
+  for (int base = tid; base < total; base += nt * U) {
+    double v[U];
+    int dst[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * nt;
+      uint32_t p, r;
+      if (d.batch_fast) {  // consecutive lanes: consecutive batch indices
+        r = fdiv((uint32_t)e, P_div);
+        p = (uint32_t)e - r * (uint32_t)P;
+      } else {             // consecutive lanes: consecutive entries of one slab
+        p = fdiv((uint32_t)e, d.size_div);
+        r = (uint32_t)e - p * (uint32_t)d.size;
+      }
+      dst[u] = -1;
+      v[u] = 0.0;
+      if (e < total && (int)p < np) {
+        int64_t g;
+        int s;
+        slab_decode(d, r, &g, &s);
+        dst[u] = (int)p * d.size + s;
+        v[u] = X[off_at(xl, l0 + p) + g];
+      }
     }
-    int64_t g;
-    int s;
-    slab_decode(d, r, &g, &s);
-    lds[p * d.size + s] = X[off_at(xl, l0 + p) + g];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (dst[u] >= 0) lds[dst[u]] = v[u];
   }
-  (void)P;
 }
 
 // One task: the slabs of batch indices l0 .. l0+P-1.  The layout comes by
@@ -57,14 +73,14 @@ __device__ inline void batched_slab(const BatchedParams& bp, const double* __res
   double* As = smem;
   double* Bs = As + P * sA;
   double* Cs = Bs + P * sB;
-  slab_load(A, bp.aL, bp.a, l0, np, P, As, tid, blockDim.x);
-  slab_load(B, bp.bL, bp.b, l0, np, P, Bs, tid, blockDim.x);
+  slab_load(A, bp.aL, bp.a, l0, np, P, bp.P_div, As, tid, blockDim.x);
+  slab_load(B, bp.bL, bp.b, l0, np, P, bp.P_div, Bs, tid, blockDim.x);
   __syncthreads();
   // outputs in canonical order [p][m][n]; n fastest
-  const int M = bp.M, N = bp.N, K = bp.K;
+  const int K = bp.K;
   for (int o = tid; o < np * sC; o += blockDim.x) {
-    const int p = o / sC, mn = o % sC;
-    const int m = mn / N, n = mn % N;
+    const uint32_t p = fdiv((uint32_t)o, bp.sC_div), mn = (uint32_t)o - p * (uint32_t)sC;
+    const uint32_t m = fdiv(mn, bp.N_div), n = mn - m * (uint32_t)bp.N;
     const double* a = As + p * sA + m * K;
     const double* b = Bs + p * sB + n * K;
     double acc = 0.0;
@@ -72,16 +88,17 @@ __device__ inline void batched_slab(const BatchedParams& bp, const double* __res
     Cs[o] = acc;
   }
   __syncthreads();
-  const int total = np * sC;
+  const int total = P * sC;
   for (int e = tid; e < total; e += blockDim.x) {
-    int p, r;
+    uint32_t p, r;
     if (bp.c.batch_fast) {
-      p = e % np;
-      r = e / np;
+      r = fdiv((uint32_t)e, bp.P_div);
+      p = (uint32_t)e - r * (uint32_t)P;
     } else {
-      p = e / sC;
-      r = e % sC;
+      p = fdiv((uint32_t)e, bp.c.size_div);
+      r = (uint32_t)e - p * (uint32_t)sC;
     }
+    if ((int)p >= np) continue;
     int64_t g;
     int s;
     slab_decode(bp.c, r, &g, &s);
@@ -89,7 +106,6 @@ __device__ inline void batched_slab(const BatchedParams& bp, const double* __res
     const double v = alpha * Cs[p * sC + s];
     *dst = beta == 0.0 ? v : v + beta * *dst;
   }
-  (void)M;
 }
 
 

@@ -52,16 +52,55 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_kernel(GettParams p, 
   __shared__ __attribute__((aligned(16))) double smem[gett_lds_doubles<BM, BN, BK>()];
   int64_t l, tm, tn;
   tile_of(blockIdx.x, total, tilesM, tilesN, &l, &tm, &tn);
-  gett_tile<BM, BN, BK, WGM, WGN, AKF, BKF>(p, tm * BM, tn * BN, l, smem);
+  gett_tile<BM, BN, BK, WGM, WGN, AKF, BKF>(p, tm * BM, tn * BN, l, smem, 0, p.K, nullptr);
+}
+
+// Split-K: workgroup (t, s) sums segment s of the contracted range for tile t.
+template <int BM, int BN, int BK, int WGM, int WGN, bool AKF, bool BKF>
+__global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_split_kernel(GettParams p, int64_t tilesM, int64_t tilesN,
+                                                                         int S, int64_t seg_len,
+                                                                         double* __restrict__ parts) {
+  __shared__ __attribute__((aligned(16))) double smem[gett_lds_doubles<BM, BN, BK>()];
+  const int64_t t = blockIdx.x / S, sg = blockIdx.x % S;
+  const int64_t per = tilesM * tilesN, l = t / per, r = t % per;
+  const int64_t kb = sg * seg_len, ke = kb + seg_len < p.K ? kb + seg_len : p.K;
+  gett_tile<BM, BN, BK, WGM, WGN, AKF, BKF>(p, (r % tilesM) * BM, (r / tilesM) * BN, l, smem, kb, ke,
+                                           parts + (t * S + sg) * (int64_t)(BM * BN));
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void gett_reduce_kernel(GettParams p, int64_t tilesM, int64_t tilesN, int S,
+                                                          const double* __restrict__ parts) {
+  const int64_t t = blockIdx.x;
+  const int64_t per = tilesM * tilesN, l = t / per, r = t % per;
+  gett_reduce_tile<BM, BN>(p, (r % tilesM) * BM, (r / tilesM) * BN, l, parts + t * S * (int64_t)(BM * BN), S);
 }
 
 template <int BM, int BN, int BK, int WGM, int WGN>
-hipError_t launch_cfg(const GettParams& p, bool akf, bool bkf, hipStream_t s) {
+hipError_t launch_cfg(const GettParams& p, bool akf, bool bkf, int S, int64_t seg_len, double* parts,
+                      hipStream_t s) {
   const int64_t tilesM = (p.M + BM - 1) / BM, tilesN = (p.N + BN - 1) / BN;
   const int64_t total = tilesM * tilesN * p.L;
   if (total == 0) return hipSuccess;
-  if (total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  dim3 grid((unsigned)total), block(64 * WGM * WGN);
+  if (total * S > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  dim3 block(64 * WGM * WGN);
+  if (S > 1) {
+    dim3 grid((unsigned)(total * S));
+#define TC_SPLIT_LAUNCH(AK, BKF_)                                                                                \
+  hipLaunchKernelGGL((gett_f64_split_kernel<BM, BN, BK, WGM, WGN, AK, BKF_>), grid, block, 0, s, p, tilesM, tilesN, \
+                     S, seg_len, parts)
+    if (akf && bkf) TC_SPLIT_LAUNCH(true, true);
+    else if (akf) TC_SPLIT_LAUNCH(true, false);
+    else if (bkf) TC_SPLIT_LAUNCH(false, true);
+    else TC_SPLIT_LAUNCH(false, false);
+#undef TC_SPLIT_LAUNCH
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((gett_reduce_kernel<BM, BN>), dim3((unsigned)total), dim3(256), 0, s, p, tilesM, tilesN, S,
+                       parts);
+    return hipGetLastError();
+  }
+  dim3 grid((unsigned)total);
   if (akf && bkf)
     hipLaunchKernelGGL((gett_f64_kernel<BM, BN, BK, WGM, WGN, true, true>), grid, block, 0, s, p, tilesM, tilesN,
                        total);
@@ -79,10 +118,11 @@ hipError_t launch_cfg(const GettParams& p, bool akf, bool bkf, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_gett_f64(const GettParams& p, int tile_id, bool a_kfast, bool b_kfast, hipStream_t s) {
+hipError_t launch_gett_f64(const GettParams& p, int tile_id, bool a_kfast, bool b_kfast, int split, int64_t seg_len,
+                           double* parts, hipStream_t s) {
   switch (tile_id) {
 #define TC_TILE(id, bm, bn, bk, wgm, wgn) \
-  case id: return launch_cfg<bm, bn, bk, wgm, wgn>(p, a_kfast, b_kfast, s);
+  case id: return launch_cfg<bm, bn, bk, wgm, wgn>(p, a_kfast, b_kfast, split, seg_len, parts, s);
     TC_GETT_TILES(TC_TILE)
 #undef TC_TILE
     default: return hipErrorInvalidValue;

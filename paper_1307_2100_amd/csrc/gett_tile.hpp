@@ -117,8 +117,13 @@ struct Frags {
   }
 };
 
+// One BM x BN tile of C at (m0, n0) in batch entry l, summing the contracted
+// range [kb, ke).  With part == nullptr the tile is finished (alpha, beta) into
+// C; otherwise its raw sums go to part[m_local * BN + n_local] (a split-K
+// segment, to be reduced by gett_reduce_tile).
 template <int BM, int BN, int BK, int WGM, int WGN, bool AKF, bool BKF>
-__device__ inline void gett_tile(const GettParams& p, int64_t m0, int64_t n0, int64_t l, double* smem) {
+__device__ inline void gett_tile(const GettParams& p, int64_t m0, int64_t n0, int64_t l, double* smem,
+                                 int64_t kb, int64_t ke, double* __restrict__ part) {
   constexpr int NT = 64 * WGM * WGN;
   using SA_ = Stage<BM, BK, AKF>;
   using SB_ = Stage<BN, BK, BKF>;
@@ -150,10 +155,10 @@ __device__ inline void gett_tile(const GettParams& p, int64_t m0, int64_t n0, in
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const int64_t ktiles = (p.K + BK - 1) / BK;
+  const int64_t ktiles = ke > kb ? (ke - kb + BK - 1) / BK : 0;
   if (ktiles > 0) {
-    la.load(A, p.aK, 0, p.K, tid);
-    lb.load(B, p.bK, 0, p.K, tid);
+    la.load(A, p.aK, kb, ke, tid);
+    lb.load(B, p.bK, kb, ke, tid);
     la.store(sA0, tid);
     lb.store(sB0, tid);
   }
@@ -165,8 +170,8 @@ __device__ inline void gett_tile(const GettParams& p, int64_t m0, int64_t n0, in
     const int cur = kt & 1;
     const bool more = kt + 1 < ktiles;
     if (more) {
-      la.load(A, p.aK, (kt + 1) * BK, p.K, tid);
-      lb.load(B, p.bK, (kt + 1) * BK, p.K, tid);
+      la.load(A, p.aK, kb + (kt + 1) * BK, ke, tid);
+      lb.load(B, p.bK, kb + (kt + 1) * BK, ke, tid);
     }
     Frags<BM, BK, AKF, TM> fa;
     Frags<BN, BK, BKF, TN> fb;
@@ -188,6 +193,16 @@ __device__ inline void gett_tile(const GettParams& p, int64_t m0, int64_t n0, in
 
   // Epilogue: v_mfma_f64_16x16x4f64 leaves D[lane/16 + 4*r][lane % 16] of each
   // 16x16 block in accumulator element r (rows interleaved by four).
+  if (part) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          part[(wm * WM + i * 16 + fk + 4 * r) * BN + wn * WN + j * 16 + fr] = acc[i][j][r];
+    return;
+  }
   double* __restrict__ C = p.C + off_at(p.cL, l);
   int64_t cn[TN];
 #pragma unroll
@@ -211,6 +226,25 @@ __device__ inline void gett_tile(const GettParams& p, int64_t m0, int64_t n0, in
         *dst = v;
       }
     }
+  }
+}
+
+// Finishes a split-K tile: adds the S segment sums of each entry in segment
+// order (a fixed order, so the result does not depend on which workgroup
+// finished last) and writes alpha * sum + beta * C.
+template <int BM, int BN>
+__device__ inline void gett_reduce_tile(const GettParams& p, int64_t m0, int64_t n0, int64_t l,
+                                        const double* __restrict__ parts, int S) {
+  double* __restrict__ C = p.C + off_at(p.cL, l);
+  for (int e = threadIdx.x; e < BM * BN; e += blockDim.x) {
+    const int64_t m = m0 + e / BN, n = n0 + e % BN;
+    if (m >= p.M || n >= p.N) continue;
+    double v = 0.0;
+    for (int sg = 0; sg < S; ++sg) v += parts[(int64_t)sg * BM * BN + e];
+    double* dst = C + off_at(p.cM, m) + off_at(p.cN, n);
+    v *= p.alpha;
+    if (p.beta != 0.0) v += p.beta * *dst;
+    *dst = v;
   }
 }
 

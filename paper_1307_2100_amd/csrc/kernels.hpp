@@ -12,6 +12,27 @@ constexpr int kMaxRank = 16;
 
 // Offsets of one operand along one index group: a table of per-index
 // offsets, or (tab == nullptr) an affine map idx * stride.
+// Division by a divisor fixed at plan time, for 0 <= n < 2^31: multiply by
+// ceil(2^p / d) and shift (p = 31 + ceil(log2 d)); d = 1 divides trivially.
+struct FastDiv {
+  uint32_t d, mul, shift;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f{d, 0u, 0u};
+  if (d <= 1) return f;
+  int l = 0;
+  while ((1u << l) < d) ++l;
+  const uint64_t p = 31 + (uint64_t)l;
+  f.mul = (uint32_t)(((1ull << p) + d - 1) / d);
+  f.shift = (uint32_t)(p - 32);
+  return f;
+}
+__device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  return f.d == 1 ? n : (__umulhi(n, f.mul) >> f.shift);
+}
+
+// Offsets of one operand along one index group: a table of per-index
+// offsets, or (tab == nullptr) an affine map idx * stride.
 struct Offs {
   const int64_t* tab;
   int64_t stride;
@@ -64,7 +85,11 @@ struct GettParams {
   X(10, 128, 128, 16, 4, 4)   \
   X(11, 256, 128, 16, 4, 4)   \
   X(12, 128, 256, 16, 4, 4)   \
-  X(13, 128, 128, 32, 2, 4)
+  X(13, 128, 128, 32, 2, 4)   \
+  X(14, 32, 32, 64, 2, 2)     \
+  X(15, 64, 64, 32, 2, 2)     \
+  X(16, 32, 32, 128, 2, 2)    \
+  X(17, 64, 64, 64, 2, 2)
 struct TileCfg {
   int id, bm, bn, bk, wgm, wgn;
 };
@@ -73,7 +98,25 @@ constexpr TileCfg kTiles[] = {TC_GETT_TILES(TC_TILE_ENTRY)};
 #undef TC_TILE_ENTRY
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
-hipError_t launch_gett_f64(const GettParams& p, int tile_id, bool a_kfast, bool b_kfast, hipStream_t s);
+// split > 1: the contracted range is cut into `split` segments of seg_len
+// (a multiple of the tile depth); parts holds tiles * split * BM * BN doubles.
+hipError_t launch_gett_f64(const GettParams& p, int tile_id, bool a_kfast, bool b_kfast, int split, int64_t seg_len,
+                           double* parts, hipStream_t s);
+// Split-K choice for `tiles` output tiles of depth-`bk` steps over K.
+inline void choose_split(int64_t tiles, int64_t K, int bk, int* split, int64_t* seg_len) {
+  *split = 1;
+  *seg_len = K;
+  if (tiles >= 128 || K < 2048) return;
+  int64_t S = (512 + tiles - 1) / tiles;
+  const int64_t cap = K / 256;  // at least 256 contracted indices per segment
+  if (S > cap) S = cap;
+  if (S > 256) S = 256;
+  if (S <= 1) return;
+  int64_t len = (K + S - 1) / S;
+  len = (len + bk - 1) / bk * bk;
+  *split = (int)((K + len - 1) / len);
+  *seg_len = len;
+}
 
 // GEMV / GER family: one thread per output entry walking the contracted
 // index (consecutive lanes along n when n_fastest, else along m).
@@ -128,7 +171,8 @@ struct SlabDesc {
   int n;                 // modes of the operand inside one slab
   int size;              // entries per slab
   int batch_fast;        // the batch index varies fastest in memory
-  int ext[kMaxRank];     // extents, sorted by global stride
+  FastDiv size_div;      // division by size
+  FastDiv div[kMaxRank];   // extents, sorted by global stride
   int64_t gstr[kMaxRank];  // global strides
   int lstr[kMaxRank];    // strides in the canonical LDS slab
 };
@@ -140,10 +184,11 @@ struct BatchedParams {
   SlabDesc a, b, c;
   int M, N, K;           // per-point group sizes
   int P;                 // batch indices per workgroup
+  FastDiv P_div, N_div, sC_div;
   int64_t L;
   double alpha, beta;
 };
-constexpr int kBatchedLdsDoubles = 8192;  // 64 KB of LDS per workgroup
+constexpr int kBatchedLdsDoubles = 2048;  // 16 KB of LDS per workgroup: several workgroups per CU
 hipError_t launch_batched_small(const BatchedParams& bp, hipStream_t s);
 
 // Persistent batches.  Tile configurations of the batch kernel (id, rows,
@@ -151,18 +196,25 @@ hipError_t launch_batched_small(const BatchedParams& bp, hipStream_t s);
 #define TC_BATCH_TILES(X) \
   X(0, 64, 64, 16)        \
   X(1, 32, 32, 16)        \
-  X(2, 128, 64, 16)       \
-  X(3, 64, 128, 16)
-constexpr int kNumBatchTiles = 4;
-constexpr int kBatchTileBM[kNumBatchTiles] = {64, 32, 128, 64};
-constexpr int kBatchTileBN[kNumBatchTiles] = {64, 32, 64, 128};
-constexpr int kBatchSlabLdsDoubles = 4096;  // slab LDS of batch tasks (32 KB)
+  X(2, 32, 32, 64)        \
+  X(3, 64, 64, 32)        \
+  X(4, 32, 32, 128)       \
+  X(5, 64, 64, 64)
+constexpr int kNumBatchTiles = 6;
+constexpr int kBatchTileBM[kNumBatchTiles] = {64, 32, 32, 64, 32, 64};
+constexpr int kBatchTileBN[kNumBatchTiles] = {64, 32, 32, 64, 32, 64};
+constexpr int kBatchSlabLdsDoubles = 2048;  // slab LDS of batch tasks (16 KB)
 struct BatchItem {       // one contraction of a batch (layout only)
   GettParams g;          // kind 0: GEMM tiles
   BatchedParams b;       // kind 1: slabs of batch indices
   int kind;
   int akf, bkf, swapped;
   int64_t tilesM, tilesN;
+  int ksplit;            // kind 0: contracted segments per tile (1 = none)
+  int pad;
+  int64_t seg_len;       // contracted indices per segment
+  int64_t part_off;      // first partial tile of this item (in tiles of BM*BN doubles)
+  int64_t cnt_off;       // first tile counter of this item
 };
 struct BatchPtrs {       // per execution
   const double* A;
@@ -172,7 +224,7 @@ struct BatchPtrs {       // per execution
 };
 struct BatchTask {
   int item;
-  int pad;
+  int seg;               // contracted segment (kind 0 with ksplit > 1)
   int64_t idx;           // tile index (kind 0) or slab index (kind 1)
 };
 struct BatchLaunch {
@@ -180,7 +232,12 @@ struct BatchLaunch {
   const BatchPtrs* ptrs;
   const BatchTask* tasks;
   int64_t ntasks;
+  const int64_t* chunks;       // chunk c holds tasks [chunks[c], chunks[c+1])
+  int64_t nchunks;
   unsigned long long* counter;
+  double* parts;               // partial tiles of split items
+  unsigned* tile_cnt;          // segments finished per split tile
+  int64_t n_cnt;
   int config;
   int slab_lds_doubles;
   int num_cus;

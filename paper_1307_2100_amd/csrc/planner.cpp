@@ -147,7 +147,7 @@ bool batched_fits(const tc_plan_info& info, const Group* G) {
   if (G[GL].n == 0 || info.L < 64) return false;
   if (info.M > 1024 || info.N > 1024 || info.K > 1024) return false;
   const int64_t per = info.M * info.K + info.N * info.K + info.M * info.N;
-  return per * 4 <= kBatchedLdsDoubles;
+  return per * 2 <= kBatchedLdsDoubles;
 }
 
 // Slab descriptors: each operand's non-batch modes sorted by global stride,
@@ -281,6 +281,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
   info.split_slices = opt.split_slices;
   info.copy_operand = -1;
   info.tile_id = -1;
+  info.k_split = 1;
   info.unit_a = unit_mode(A0);
   info.unit_b = unit_mode(B0);
   info.unit_c = unit_mode(C0);
@@ -477,6 +478,19 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     build_slabs(an);
   } else if (recipe == TC_RECIPE_GEMM || recipe == TC_RECIPE_COPY_GEMM) {
     info.tile_id = opt.tile_id >= 0 ? opt.tile_id : pick_tile(info.M, info.N, info.L);
+    // few output tiles over a long contracted range: cut the range into
+    // segments so that more workgroups share the work (split-K)
+    const TileCfg& t = kTiles[info.tile_id];
+    const int64_t tiles = ((info.M + t.bm - 1) / t.bm) * ((info.N + t.bn - 1) / t.bn) * info.L;
+    int split = 1;
+    int64_t len = info.K;
+    if (!an.empty_out && !an.empty_sum) choose_split(tiles, info.K, t.bk, &split, &len);
+    info.k_split = split;
+    an.seg_len = len;
+    if (split > 1) {
+      an.part_offset = (info.workspace_bytes + 255) / 256 * 256;
+      info.workspace_bytes = an.part_offset + (size_t)tiles * split * t.bm * t.bn * sizeof(double);
+    }
   } else {
     // Memory-bound recipes (Sec. 3.2, Classes 1 and 2, and the GER slicing).
     // GER sums its rank-1 updates in registers, one thread per output entry.

@@ -63,6 +63,7 @@ struct Analysis {
   bool n_fastest = false;   // lanes-over-outputs: consecutive lanes along n
   int64_t seg = 1;          // lanes-over-k: contracted segments per output
   size_t part_offset = 0;   // byte offset of the partial sums in the workspace
+  int64_t seg_len = 0;      // split-K GEMM: contracted indices per segment
   bool a_mfast = false;     // kernel A's stride-1 mode leads its free group
   bool b_nfast = false;     // kernel B's stride-1 mode leads its free group
   // split precision: padded sizes of the digit planes and workspace offsets

@@ -221,3 +221,21 @@ def test_split_precision_plans_have_no_copy_step():
     assert info.workspace_bytes > 0
     info = analyze("abg", "gah", "bh", ext, precision="split_fp8")
     assert info.split_slices == 8
+
+
+def test_fast_division_method():
+    """The slab engine divides by plan-time constants with a multiply and a
+    shift (mul = ceil(2^p / d), p = 31 + ceil(log2 d)); check the method
+    against exact integer division on 0 <= n < 2^31."""
+    g = np.random.default_rng(17)
+    divisors = list(range(1, 3000)) + [int(x) for x in g.integers(3000, 1 << 30, 300)] + [(1 << 30) + 1, (1 << 31) - 1]
+    for d in divisors:
+        if d == 1:
+            continue
+        l = (d - 1).bit_length()
+        p = 31 + l
+        mul = ((1 << p) + d - 1) // d
+        assert mul < (1 << 32)
+        ns = [0, 1, d - 1, d, d + 1, (1 << 31) - 1, (1 << 31) - 2] + [int(x) for x in g.integers(0, 1 << 31, 50)]
+        for n in ns:
+            assert ((n * mul) >> 32) >> (p - 32) == n // d, (n, d)

@@ -19,7 +19,9 @@ import paper_1307_2100_amd as tc  # noqa: E402
 
 def _make_batch(count, seed, kind="integers"):
     g = np.random.default_rng(seed)
-    specs = [synth.workload_gr_r((6, 5, 4)), synth.workload_gr_s((6, 5, 4))]
+    specs = [synth.workload_gr_r((6, 5, 4)), synth.workload_gr_s((6, 5, 4)),
+             ("akb", "kbc", "ac", {"a": 31, "k": 300, "b": 37, "c": 5}),      # split-K tasks
+             ("ikm", "kj", "ijm", {"i": 70, "k": 3000, "m": 2, "j": 9})]
     for _ in range(count):
         specs.append(synth.random_contraction(g, rank_range=(3, 6), ext_range=(2, 9), max_elems=20000,
                                               p_outer=0.03, allow_batch=True))
@@ -90,7 +92,7 @@ def test_autotune_keeps_results_and_new_buffers():
     batch, entries = _make_batch(30, 13)
     As, Bs, Cs = [e["dA"] for e in entries], [e["dB"] for e in entries], [e["C"] for e in entries]
     best, ms = batch.autotune(As, Bs, Cs)
-    assert 0 <= best < 4 and ms > 0
+    assert 0 <= best < 6 and ms > 0
     assert batch.query()["tile_config"] == best
     # fresh output buffers: the graph reads pointers at every replay
     Cs2 = [torch.zeros_like(c) for c in Cs]

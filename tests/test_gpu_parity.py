@@ -35,6 +35,7 @@ CASES = [
     ("batch", "acbdx", "cdx", "abx", {"a": 4, "b": 4, "c": 4, "d": 4, "x": 300}),
     ("c_nonunit_n", "ki", "kj", "ji", {"i": 70, "j": 90, "k": 200}),
     ("long_k", "ik", "kj", "ij", {"i": 65, "j": 66, "k": 3000}),
+    ("split_k", "akb", "kbc", "ac", {"a": 31, "k": 600, "b": 37, "c": 5}),   # few tiles, long sum
 ]
 
 
@@ -177,3 +178,12 @@ def test_memory_bound_recipes(case):
     got, info = _run(labA, labB, labC, A, B, "auto", alpha=0.5)
     ref, absr = reference(A, labA, B, labB, labC, alpha=0.5)
     assert componentwise_error(got, ref, absr) <= FP64_TOL
+
+
+def test_split_k_is_used_and_exact():
+    labA, labB, labC, ext = "akb", "kbc", "ac", {"a": 31, "k": 600, "b": 37, "c": 5}
+    A, B = synth.make_operands(14, labA, labB, ext, kind="integers")
+    for recipe in ("auto", "gemm", "copy_gemm"):
+        got, info = _run(labA, labB, labC, A, B, recipe)
+        assert info["k_split"] > 1, info
+        assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
