@@ -108,6 +108,7 @@ typedef struct {
   int kernel;                  /* kernel family: 0 MFMA GEMM, 1 lanes over outputs, 2 lanes over k,
                                   3 batched small slabs, 4 split-precision digits */
   int k_split;                 /* MFMA GEMM: segments of the contracted range (1 = none) */
+  int picked_candidate;        /* candidate chosen by the MLP or the tune cache, -1: rules */
 } tc_plan_info;
 
 /* Fills *opt with the defaults listed in tc_options. */
@@ -186,6 +187,73 @@ tc_status tc_batch_autotune(tc_batch_t batch, const double* const* A, const doub
                             void* workspace, size_t workspace_bytes, void* stream,
                             int* best_config, double* best_ms);
 tc_status tc_batch_destroy(tc_batch_t batch);
+
+/* ---------------------------------------------------------------------------
+ * Learned recipe/tile picker (an addition to the paper; the paper's class
+ * rules, Sec. 3.2, remain the fallback and numerical results never depend on
+ * the choice).  A contraction is described by TC_PICKER_FEATURES features of
+ * its layout; an MLP predicts the log execution time of each of the
+ * TC_PICKER_CANDIDATES (recipe, tile) candidates, and the plan takes the
+ * fastest.  The MLP is trained on the GPU by the tc_mlp_* kernels.
+ * ------------------------------------------------------------------------- */
+#define TC_PICKER_FEATURES 32
+#define TC_PICKER_CANDIDATES 15
+
+/* Candidate `index` (0 .. TC_PICKER_CANDIDATES-1): recipe and GEMM tile id
+ * (-1 for the memory-bound recipes).  The last candidate is TC_RECIPE_AUTO:
+ * the rules' own plan, whatever kernel it takes. */
+tc_status tc_picker_candidate(int index, tc_recipe* recipe, int* tile_id);
+
+/* Host only: the features of a contraction (arguments as tc_analyze; feat
+ * receives TC_PICKER_FEATURES floats) and the candidate the rules would take
+ * (*rule_candidate, -1 when the rules pick a kernel outside the table). */
+tc_status tc_picker_features(int rank_a, const int64_t* ext_a, const int64_t* str_a, const int32_t* lab_a,
+                             int rank_b, const int64_t* ext_b, const int64_t* str_b, const int32_t* lab_b,
+                             int rank_c, const int64_t* ext_c, const int64_t* str_c, const int32_t* lab_c,
+                             float* feat, int* rule_candidate);
+
+/* Installs a trained model for TC_PICKER_MLP plans of this process (copies
+ * the host arrays; creates the network on the current device): params in the
+ * tc_mlp layout, n_in must be TC_PICKER_FEATURES and n_out
+ * TC_PICKER_CANDIDATES; mean/std normalise the features.  Replaces any
+ * previous model.  tc_picker_uninstall returns to the rules. */
+tc_status tc_picker_install(const float* params, int64_t n_params, int n_in, int hidden, int n_out,
+                            const float* feat_mean, const float* feat_std);
+tc_status tc_picker_uninstall(void);
+
+/* Autotuner for one shape: times every candidate on the given buffers (C is
+ * overwritten with beta = 0; after a warm-up, the median of three timed runs,
+ * each of enough back-to-back executions to last about 0.2 ms; the library
+ * allocates the candidates' workspaces itself), records the fastest in the
+ * process-wide tune cache used by TC_PICKER_TUNED plans of the same shape, and
+ * returns it.  candidate_ms (NULL, or TC_PICKER_CANDIDATES doubles) receives
+ * each candidate's time per execution in milliseconds, -1 for a candidate the
+ * shape cannot take. */
+tc_status tc_plan_autotune(tc_plan_t plan, const double* A, const double* B, double* C, void* stream,
+                           int* best_candidate, double* best_ms, double* candidate_ms);
+/* The tune cache as a text file (one line per shape: library version, device
+ * architecture, shape signature, candidate); entries of another version or
+ * architecture are ignored on load. */
+tc_status tc_tune_cache_save(const char* path);
+tc_status tc_tune_cache_load(const char* path);
+
+/* The MLP itself: n_in -> hidden -> hidden -> n_out, ReLU, FP32, weights
+ * row-major W[i][o] followed by biases, layer by layer.  All X/T/M/Y/grads/loss
+ * pointers are DEVICE pointers (row-major batch x width); batch <= max_batch.
+ * loss_grad: forward, masked mean-squared error sum(M (Y-T)^2) / sum(M) into
+ * *loss, and its gradient into grads (either may be NULL).  train_step: the
+ * same followed by one Adam step (beta 0.9, 0.999, eps 1e-8). */
+typedef struct tc_mlp_s* tc_mlp_t;
+tc_status tc_mlp_create(tc_mlp_t* out, int n_in, int hidden, int n_out, int max_batch);
+tc_status tc_mlp_num_params(tc_mlp_t mlp, int64_t* n);
+tc_status tc_mlp_set_params(tc_mlp_t mlp, const float* host_params);
+tc_status tc_mlp_get_params(tc_mlp_t mlp, float* host_params);
+tc_status tc_mlp_forward(tc_mlp_t mlp, const float* X, float* Y, int batch, void* stream);
+tc_status tc_mlp_loss_grad(tc_mlp_t mlp, const float* X, const float* T, const float* M, int batch, float* grads,
+                           float* loss, void* stream);
+tc_status tc_mlp_train_step(tc_mlp_t mlp, const float* X, const float* T, const float* M, int batch, float lr,
+                            float* loss, void* stream);
+tc_status tc_mlp_destroy(tc_mlp_t mlp);
 
 const char* tc_status_string(tc_status s);
 const char* tc_last_error(void);

@@ -47,6 +47,7 @@ KERNEL_NAMES = {0: "mfma_gemm", 1: "lanes_over_outputs", 2: "lanes_over_k", 3: "
 NUM_TILES = 18
 # tc_picker
 TC_PICKER_RULES, TC_PICKER_MLP, TC_PICKER_TUNED = 0, 1, 2
+PICKERS = {"rules": 0, "mlp": 1, "tuned": 2}
 
 
 class tc_options(ctypes.Structure):
@@ -63,7 +64,7 @@ class tc_plan_info(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t), ("precision", ctypes.c_int),
                 ("split_slices", ctypes.c_int), ("kernel", ctypes.c_int),
-                ("k_split", ctypes.c_int)]
+                ("k_split", ctypes.c_int), ("picked_candidate", ctypes.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -110,6 +111,42 @@ _lib.tc_batch_autotune.argtypes = _lib.tc_batch_execute.argtypes + [ctypes.POINT
 _lib.tc_batch_autotune.restype = ctypes.c_int
 _lib.tc_batch_destroy.argtypes = [ctypes.c_void_p]
 _lib.tc_batch_destroy.restype = ctypes.c_int
+_FP = ctypes.POINTER(ctypes.c_float)
+_lib.tc_picker_candidate.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.tc_picker_candidate.restype = ctypes.c_int
+_lib.tc_picker_features.argtypes = _DESC * 3 + [_FP, ctypes.POINTER(ctypes.c_int)]
+_lib.tc_picker_features.restype = ctypes.c_int
+_lib.tc_picker_install.argtypes = [_FP, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _FP, _FP]
+_lib.tc_picker_install.restype = ctypes.c_int
+_lib.tc_picker_uninstall.argtypes = []
+_lib.tc_picker_uninstall.restype = ctypes.c_int
+_lib.tc_plan_autotune.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
+_lib.tc_plan_autotune.restype = ctypes.c_int
+_lib.tc_tune_cache_save.argtypes = [ctypes.c_char_p]
+_lib.tc_tune_cache_save.restype = ctypes.c_int
+_lib.tc_tune_cache_load.argtypes = [ctypes.c_char_p]
+_lib.tc_tune_cache_load.restype = ctypes.c_int
+_lib.tc_mlp_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                               ctypes.c_int]
+_lib.tc_mlp_create.restype = ctypes.c_int
+_lib.tc_mlp_num_params.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
+_lib.tc_mlp_num_params.restype = ctypes.c_int
+_lib.tc_mlp_set_params.argtypes = [ctypes.c_void_p, _FP]
+_lib.tc_mlp_set_params.restype = ctypes.c_int
+_lib.tc_mlp_get_params.argtypes = [ctypes.c_void_p, _FP]
+_lib.tc_mlp_get_params.restype = ctypes.c_int
+_lib.tc_mlp_forward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+_lib.tc_mlp_forward.restype = ctypes.c_int
+_lib.tc_mlp_loss_grad.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.tc_mlp_loss_grad.restype = ctypes.c_int
+_lib.tc_mlp_train_step.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]
+_lib.tc_mlp_train_step.restype = ctypes.c_int
+_lib.tc_mlp_destroy.argtypes = [ctypes.c_void_p]
+_lib.tc_mlp_destroy.restype = ctypes.c_int
 _lib.tc_status_string.argtypes = [ctypes.c_int]
 _lib.tc_status_string.restype = ctypes.c_char_p
 _lib.tc_last_error.restype = ctypes.c_char_p
@@ -118,7 +155,13 @@ _lib.tc_version.restype = ctypes.c_char_p
 EXPORTED = ["tc_options_default", "tc_analyze", "tc_plan_create", "tc_plan_query", "tc_execute",
             "tc_plan_destroy", "tc_permute", "tc_batch_create", "tc_batch_workspace", "tc_batch_execute",
             "tc_batch_set_options", "tc_batch_query", "tc_batch_autotune", "tc_batch_destroy",
-            "tc_status_string", "tc_last_error", "tc_version"]
+            "tc_picker_candidate", "tc_picker_features", "tc_picker_install", "tc_picker_uninstall",
+            "tc_plan_autotune", "tc_tune_cache_save", "tc_tune_cache_load", "tc_mlp_create", "tc_mlp_num_params",
+            "tc_mlp_set_params", "tc_mlp_get_params", "tc_mlp_forward", "tc_mlp_loss_grad", "tc_mlp_train_step",
+            "tc_mlp_destroy", "tc_status_string", "tc_last_error", "tc_version"]
+
+PICKER_FEATURES = 32
+PICKER_CANDIDATES = 15
 
 
 class TCError(RuntimeError):
@@ -170,7 +213,7 @@ def make_options(precision="f64", recipe="auto", picker=0, split_slices=0, tile_
     _lib.tc_options_default(ctypes.byref(o))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.recipe = RECIPES[recipe] if isinstance(recipe, str) else int(recipe)
-    o.picker = int(picker)
+    o.picker = PICKERS[picker] if isinstance(picker, str) else int(picker)
     o.split_slices = int(split_slices)
     o.tile_id = int(tile_id)
     return o
@@ -217,6 +260,44 @@ def tc_permute(extents, strides_x, strides_y, X_ptr, Y_ptr, stream):
     sx = (ctypes.c_int64 * n)(*[int(v) for v in strides_x])
     sy = (ctypes.c_int64 * n)(*[int(v) for v in strides_y])
     _check(_lib.tc_permute(len(extents), e, sx, sy, X_ptr, Y_ptr, stream))
+
+
+def tc_picker_candidate(index):
+    """(recipe, tile_id) of picker candidate `index`."""
+    r = ctypes.c_int()
+    t = ctypes.c_int()
+    _check(_lib.tc_picker_candidate(int(index), ctypes.byref(r), ctypes.byref(t)))
+    return r.value, t.value
+
+
+def tc_picker_features(dA, dB, dC):
+    """(features as a list of PICKER_FEATURES floats, the rules' candidate)."""
+    f = (ctypes.c_float * PICKER_FEATURES)()
+    rc = ctypes.c_int()
+    _check(_lib.tc_picker_features(*dA.args(), *dB.args(), *dC.args(), f, ctypes.byref(rc)))
+    return list(f), rc.value
+
+
+def _farr(values):
+    values = [float(v) for v in values]
+    return (ctypes.c_float * max(1, len(values)))(*values)
+
+
+def tc_picker_install(params, hidden, mean, std):
+    _check(_lib.tc_picker_install(_farr(params), len(params), PICKER_FEATURES, int(hidden), PICKER_CANDIDATES,
+                                  _farr(mean), _farr(std)))
+
+
+def tc_picker_uninstall():
+    _check(_lib.tc_picker_uninstall())
+
+
+def tc_tune_cache_save(path):
+    _check(_lib.tc_tune_cache_save(os.fsencode(path)))
+
+
+def tc_tune_cache_load(path):
+    _check(_lib.tc_tune_cache_load(os.fsencode(path)))
 
 
 def tc_status_string(status):
@@ -281,6 +362,21 @@ class Plan:
         tc_execute(self.handle, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
                    ctypes.c_void_p(C.data_ptr()), alpha, beta, wptr, wbytes, _stream_handle(stream))
         return C
+
+    def autotune(self, A, B, C, stream=None):
+        """Times every picker candidate on these buffers (C is overwritten);
+        records the fastest in the tune cache; returns (candidate, ms, list of
+        per-candidate ms with -1 where a candidate cannot run)."""
+        _require_f64_cuda(A, "A")
+        _require_f64_cuda(B, "B")
+        _require_f64_cuda(C, "C")
+        best = ctypes.c_int()
+        ms = ctypes.c_double()
+        per = (ctypes.c_double * PICKER_CANDIDATES)()
+        _check(_lib.tc_plan_autotune(self.handle, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                     ctypes.c_void_p(C.data_ptr()), _stream_handle(stream), ctypes.byref(best),
+                                     ctypes.byref(ms), per))
+        return best.value, ms.value, list(per)
 
     def close(self):
         if getattr(self, "handle", None) is not None:
@@ -399,6 +495,76 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None) is not None:
             _lib.tc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ the MLP
+class MLP:
+    """The picker's network (n_in -> hidden -> hidden -> n_out, ReLU, FP32),
+    trained and evaluated by libtc's HIP kernels.  Batches are float32 CUDA
+    tensors, row-major (batch, width)."""
+
+    def __init__(self, n_in, hidden, n_out, max_batch):
+        h = ctypes.c_void_p()
+        _check(_lib.tc_mlp_create(ctypes.byref(h), int(n_in), int(hidden), int(n_out), int(max_batch)))
+        self.handle = h
+        self.n_in, self.hidden, self.n_out, self.max_batch = n_in, hidden, n_out, max_batch
+        n = ctypes.c_int64()
+        _check(_lib.tc_mlp_num_params(h, ctypes.byref(n)))
+        self.num_params = n.value
+
+    def set_params(self, values):
+        if len(values) != self.num_params:
+            raise ValueError("need %d parameters" % self.num_params)
+        _check(_lib.tc_mlp_set_params(self.handle, _farr(values)))
+
+    def get_params(self):
+        buf = (ctypes.c_float * self.num_params)()
+        _check(_lib.tc_mlp_get_params(self.handle, buf))
+        return list(buf)
+
+    @staticmethod
+    def _f32(t, name, cols):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32 \
+                or not t.is_contiguous() or t.dim() != 2 or t.shape[1] != cols:
+            raise TypeError("%s must be a contiguous float32 CUDA tensor of width %d" % (name, cols))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def forward(self, X, stream=None):
+        torch = _torch()
+        x = self._f32(X, "X", self.n_in)
+        Y = torch.empty((X.shape[0], self.n_out), dtype=torch.float32, device=X.device)
+        _check(_lib.tc_mlp_forward(self.handle, x, ctypes.c_void_p(Y.data_ptr()), X.shape[0],
+                                   _stream_handle(stream)))
+        return Y
+
+    def loss_grad(self, X, T, M, stream=None):
+        """(loss, flat gradient) as CUDA tensors."""
+        torch = _torch()
+        args = (self._f32(X, "X", self.n_in), self._f32(T, "T", self.n_out), self._f32(M, "M", self.n_out))
+        g = torch.empty(self.num_params, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        _check(_lib.tc_mlp_loss_grad(self.handle, *args, X.shape[0], ctypes.c_void_p(g.data_ptr()),
+                                     ctypes.c_void_p(loss.data_ptr()), _stream_handle(stream)))
+        return loss, g
+
+    def train_step(self, X, T, M, lr, loss=None, stream=None):
+        """One Adam step; the loss before the step goes to `loss` (a 1-element
+        float32 CUDA tensor) when given."""
+        args = (self._f32(X, "X", self.n_in), self._f32(T, "T", self.n_out), self._f32(M, "M", self.n_out))
+        lp = ctypes.c_void_p(loss.data_ptr()) if loss is not None else None
+        _check(_lib.tc_mlp_train_step(self.handle, *args, X.shape[0], float(lr), lp, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            _lib.tc_mlp_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -2,7 +2,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <new>
 #include <string>
 #include <vector>
@@ -124,6 +129,113 @@ struct tc_plan_s {
   // per-group offsets of each kernel operand (A: M,K,L; B: N,K,L; C: M,N,L)
   tc::Offs aM{}, aK{}, aL{}, bN{}, bK{}, bL{}, cM{}, cN{}, cL{};
 };
+
+// The picker's network on the device: parameters, Adam moments, gradients
+// and the activations of one batch of at most max_batch rows.
+struct tc_mlp_s {
+  tc::MlpDims d{};
+  int max_batch = 0;
+  int step = 0;
+  float* params = nullptr;
+  float* grads = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  float* sums = nullptr;
+  tc::MlpScratch w{};
+  std::vector<float*> owned;
+  ~tc_mlp_s() {
+    for (float* p : owned) (void)hipFree(p);
+  }
+  hipError_t alloc(float** p, int64_t n) {
+    hipError_t e = hipMalloc((void**)p, (size_t)(n > 0 ? n : 1) * sizeof(float));
+    if (e == hipSuccess) owned.push_back(*p);
+    return e;
+  }
+  hipError_t init() {
+    const int64_t np = d.num_params(), B = max_batch;
+    hipError_t e;
+    if ((e = alloc(&params, np)) || (e = alloc(&grads, np)) || (e = alloc(&m, np)) || (e = alloc(&v, np)) ||
+        (e = alloc(&sums, 2)) || (e = alloc(&w.H1, B * d.hidden)) || (e = alloc(&w.H2, B * d.hidden)) ||
+        (e = alloc(&w.Y, B * d.n_out)) || (e = alloc(&w.dY, B * d.n_out)) || (e = alloc(&w.dH2, B * d.hidden)) ||
+        (e = alloc(&w.dH1, B * d.hidden)))
+      return e;
+    if ((e = hipMemset(m, 0, np * sizeof(float))) || (e = hipMemset(v, 0, np * sizeof(float)))) return e;
+    return hipSuccess;
+  }
+};
+
+namespace {
+
+// The model TC_PICKER_MLP plans consult, and the tune cache of TC_PICKER_TUNED.
+struct Picker {
+  std::mutex mu;
+  tc_mlp_s* net = nullptr;
+  int device = -1;
+  std::vector<float> mean, stdev;
+  float* d_in = nullptr;
+  float* d_out = nullptr;
+  std::map<std::string, int> tune;  // shape signature -> candidate
+  void drop() {
+    delete net;
+    net = nullptr;
+    if (d_in) (void)hipFree(d_in);
+    if (d_out) (void)hipFree(d_out);
+    d_in = d_out = nullptr;
+  }
+};
+Picker g_picker;
+
+// Candidates ordered by predicted time, fastest first (empty without a model
+// for the current device, or on failure).
+std::vector<int> picker_order(const float* feat) {
+  std::vector<int> order;
+  std::lock_guard<std::mutex> lock(g_picker.mu);
+  if (!g_picker.net) return order;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != g_picker.device) return order;
+  float x[TC_PICKER_FEATURES], y[TC_PICKER_CANDIDATES];
+  for (int i = 0; i < TC_PICKER_FEATURES; ++i)
+    x[i] = (feat[i] - g_picker.mean[i]) / (g_picker.stdev[i] > 0.f ? g_picker.stdev[i] : 1.f);
+  tc_mlp_s* n = g_picker.net;
+  if (hipMemcpy(g_picker.d_in, x, sizeof(x), hipMemcpyHostToDevice) != hipSuccess) return order;
+  if (tc::mlp_forward(n->d, n->params, g_picker.d_in, n->w.H1, n->w.H2, g_picker.d_out, 1, nullptr) != hipSuccess)
+    return order;
+  if (hipMemcpy(y, g_picker.d_out, sizeof(y), hipMemcpyDeviceToHost) != hipSuccess) return order;
+  for (int c = 0; c < TC_PICKER_CANDIDATES; ++c) order.push_back(c);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return y[a] < y[b]; });
+  return order;
+}
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+// A shape's signature: extents, strides and label pattern of A, B and C.
+std::string shape_signature(const tc::TensorDesc* d) {
+  std::ostringstream os;
+  for (int t = 0; t < 3; ++t) {
+    os << (t ? "|" : "");
+    for (int i = 0; i < d[t].rank; ++i) {
+      // labels renumbered by first appearance, so that renaming does not matter
+      int idx = 0;
+      bool found = false;
+      for (int u = 0; u < 3 && !found; ++u)
+        for (int j = 0; j < d[u].rank && !found; ++j) {
+          if (d[u].lab[j] == d[t].lab[i]) found = true;
+          else idx++;
+        }
+      os << idx << ":" << d[t].ext[i] << ":" << d[t].str[i] << ",";
+    }
+  }
+  return os.str();
+}
+
+}  // namespace
 
 // A batch: items (layouts of its contractions) and the task list of the
 // current tile configuration live on the device; pointers and scalars go
@@ -368,6 +480,33 @@ tc_status tc_plan_create(tc_plan_t* out, int ra, const int64_t* ea, const int64_
   if (s != TC_OK) {
     delete p;
     return s;
+  }
+  p->an.info.picked_candidate = -1;
+  if (p->opt.precision == TC_PREC_F64 && p->opt.recipe == TC_RECIPE_AUTO && p->opt.tile_id < 0 &&
+      (p->opt.picker == TC_PICKER_MLP || p->opt.picker == TC_PICKER_TUNED)) {
+    std::vector<int> order;
+    if (p->opt.picker == TC_PICKER_MLP) {
+      float f[TC_PICKER_FEATURES];
+      tc::picker_features(p->an, p->desc[0], p->desc[1], p->desc[2], f);
+      order = picker_order(f);
+    } else {
+      std::lock_guard<std::mutex> lock(g_picker.mu);
+      auto it = g_picker.tune.find(shape_signature(p->desc));
+      if (it != g_picker.tune.end()) order.push_back(it->second);
+    }
+    // re-plan with the first candidate this shape can take; with none, keep the rules' plan
+    for (int c : order) {
+      tc_options o = p->opt;
+      o.recipe = tc::kCandidates[c].recipe;
+      o.tile_id = tc::kCandidates[c].tile;
+      tc::Analysis an2;
+      std::string err;
+      if (tc::analyze(p->desc[0], p->desc[1], p->desc[2], o, &an2, &err) == TC_OK) {
+        p->an = an2;
+        p->an.info.picked_candidate = c;
+        break;
+      }
+    }
   }
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
@@ -798,6 +937,240 @@ tc_status tc_batch_autotune(tc_batch_t batch, const double* const* A, const doub
 
 tc_status tc_batch_destroy(tc_batch_t batch) {
   delete batch;
+  return TC_OK;
+}
+
+tc_status tc_picker_candidate(int index, tc_recipe* recipe, int* tile_id) {
+  if (index < 0 || index >= TC_PICKER_CANDIDATES) return fail(TC_ERR_INVALID_ARG, "candidate index out of range");
+  if (recipe) *recipe = tc::kCandidates[index].recipe;
+  if (tile_id) *tile_id = tc::kCandidates[index].tile;
+  return TC_OK;
+}
+
+tc_status tc_picker_features(int ra, const int64_t* ea, const int64_t* sa, const int32_t* la, int rb,
+                             const int64_t* eb, const int64_t* sb, const int32_t* lb, int rc, const int64_t* ec,
+                             const int64_t* sc, const int32_t* lc, float* feat, int* rule_candidate) {
+  if (!feat) return fail(TC_ERR_INVALID_ARG, "feat is null");
+  tc::Analysis an;
+  tc::TensorDesc d[3];
+  tc_status s = analyze_args(ra, ea, sa, la, rb, eb, sb, lb, rc, ec, sc, lc, nullptr, &an, d);
+  if (s != TC_OK) return s;
+  tc::picker_features(an, d[0], d[1], d[2], feat);
+  if (rule_candidate) *rule_candidate = tc::candidate_of(an);
+  return TC_OK;
+}
+
+tc_status tc_picker_install(const float* params, int64_t n_params, int n_in, int hidden, int n_out,
+                            const float* feat_mean, const float* feat_std) {
+  if (!params || !feat_mean || !feat_std) return fail(TC_ERR_INVALID_ARG, "null model array");
+  if (n_in != TC_PICKER_FEATURES || n_out != TC_PICKER_CANDIDATES || hidden < 1 || hidden > 4096)
+    return fail(TC_ERR_INVALID_ARG, "model dimensions do not match the picker");
+  tc_mlp_t net = nullptr;
+  tc_status s = tc_mlp_create(&net, n_in, hidden, n_out, 1);
+  if (s != TC_OK) return s;
+  if (n_params != net->d.num_params()) {
+    tc_mlp_destroy(net);
+    return fail(TC_ERR_INVALID_ARG, "parameter count does not match the dimensions");
+  }
+  s = tc_mlp_set_params(net, params);
+  if (s != TC_OK) {
+    tc_mlp_destroy(net);
+    return s;
+  }
+  std::lock_guard<std::mutex> lock(g_picker.mu);
+  g_picker.drop();
+  g_picker.net = net;
+  (void)hipGetDevice(&g_picker.device);
+  g_picker.mean.assign(feat_mean, feat_mean + n_in);
+  g_picker.stdev.assign(feat_std, feat_std + n_in);
+  if (hipMalloc((void**)&g_picker.d_in, n_in * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&g_picker.d_out, n_out * sizeof(float)) != hipSuccess) {
+    g_picker.drop();
+    return fail(TC_ERR_NOMEM, "picker buffers");
+  }
+  return TC_OK;
+}
+
+tc_status tc_picker_uninstall(void) {
+  std::lock_guard<std::mutex> lock(g_picker.mu);
+  g_picker.drop();
+  return TC_OK;
+}
+
+tc_status tc_plan_autotune(tc_plan_t plan, const double* A, const double* B, double* C, void* stream,
+                           int* best_candidate, double* best_ms, double* candidate_ms) {
+  if (!plan || !A || !B || !C) return fail(TC_ERR_INVALID_ARG, "null plan or buffer");
+  hipStream_t st = (hipStream_t)stream;
+  // plans of every candidate the shape can take, and one workspace for all
+  tc_plan_t cand[TC_PICKER_CANDIDATES] = {};
+  size_t ws_max = 0;
+  const tc::TensorDesc* d = plan->desc;
+  for (int c = 0; c < TC_PICKER_CANDIDATES; ++c) {
+    tc_options o = plan->opt;
+    o.recipe = tc::kCandidates[c].recipe;
+    o.tile_id = tc::kCandidates[c].tile;
+    o.picker = TC_PICKER_RULES;
+    if (tc_plan_create(&cand[c], d[0].rank, d[0].ext, d[0].str, d[0].lab, d[1].rank, d[1].ext, d[1].str, d[1].lab,
+                       d[2].rank, d[2].ext, d[2].str, d[2].lab, &o) != TC_OK)
+      cand[c] = nullptr;  // a candidate this shape cannot take
+    else
+      ws_max = std::max(ws_max, cand[c]->an.info.workspace_bytes);
+  }
+  auto destroy_all = [&]() {
+    for (tc_plan_t& c : cand)
+      if (c) tc_plan_destroy(c), c = nullptr;
+  };
+  void* ws = nullptr;
+  if (ws_max && hipMalloc(&ws, ws_max) != hipSuccess) {
+    destroy_all();
+    return fail(TC_ERR_NOMEM, "autotune workspace");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  tc_status result = TC_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) result = fail(TC_ERR_HIP, "event create");
+  // time per execution of `reps` back-to-back executions, in ms
+  auto timed = [&](tc_plan_t cp, int reps, float* ms) -> tc_status {
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < reps; ++r) {
+      tc_status s = tc_execute(cp, A, B, C, 1.0, 0.0, ws, ws_max, stream);
+      if (s != TC_OK) return s;
+    }
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) return fail(TC_ERR_HIP, "event sync");
+    if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return fail(TC_ERR_HIP, "event time");
+    *ms /= (float)reps;
+    return TC_OK;
+  };
+  int best = -1;
+  float best_t = 0.f;
+  for (int c = 0; c < TC_PICKER_CANDIDATES && result == TC_OK; ++c) {
+    if (candidate_ms) candidate_ms[c] = -1.0;
+    if (!cand[c]) continue;
+    float t1 = 0.f, t[3] = {0.f, 0.f, 0.f};
+    result = timed(cand[c], 1, &t1);  // warm-up, and an estimate of the time
+    if (result != TC_OK) break;
+    const int reps = (int)std::min(64.0, std::max(1.0, std::ceil(0.2 / std::max(t1, 1e-4f))));
+    for (int r = 0; r < 3 && result == TC_OK; ++r) result = timed(cand[c], reps, &t[r]);
+    if (result != TC_OK) break;
+    std::sort(t, t + 3);
+    if (candidate_ms) candidate_ms[c] = t[1];
+    if (best < 0 || t[1] < best_t) {
+      best = c;
+      best_t = t[1];
+    }
+  }
+  if (result == TC_OK && hipStreamSynchronize(st) != hipSuccess) result = fail(TC_ERR_HIP, "stream sync");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (ws) (void)hipFree(ws);
+  destroy_all();
+  if (result != TC_OK) return result;
+  if (best < 0) return fail(TC_ERR_UNSUPPORTED, "no candidate could run");
+  {
+    std::lock_guard<std::mutex> lock(g_picker.mu);
+    g_picker.tune[shape_signature(plan->desc)] = best;
+  }
+  if (best_candidate) *best_candidate = best;
+  if (best_ms) *best_ms = best_t;
+  return TC_OK;
+}
+
+tc_status tc_tune_cache_save(const char* path) {
+  if (!path) return fail(TC_ERR_INVALID_ARG, "path is null");
+  std::ofstream f(path);
+  if (!f) return fail(TC_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  const std::string arch = device_arch();
+  std::lock_guard<std::mutex> lock(g_picker.mu);
+  for (auto& kv : g_picker.tune) f << TC_VERSION << " " << arch << " " << kv.first << " " << kv.second << "\n";
+  return f ? TC_OK : fail(TC_ERR_INVALID_ARG, "write failed");
+}
+
+tc_status tc_tune_cache_load(const char* path) {
+  if (!path) return fail(TC_ERR_INVALID_ARG, "path is null");
+  std::ifstream f(path);
+  if (!f) return fail(TC_ERR_INVALID_ARG, std::string("cannot read ") + path);
+  const std::string arch = device_arch();
+  std::string ver, ar, sig;
+  int c;
+  std::lock_guard<std::mutex> lock(g_picker.mu);
+  while (f >> ver >> ar >> sig >> c) {
+    if (ver != TC_VERSION || ar != arch || c < 0 || c >= TC_PICKER_CANDIDATES) continue;  // stale entry
+    g_picker.tune[sig] = c;
+  }
+  return TC_OK;
+}
+
+tc_status tc_mlp_create(tc_mlp_t* out, int n_in, int hidden, int n_out, int max_batch) {
+  if (!out) return fail(TC_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (n_in < 1 || hidden < 1 || n_out < 1 || max_batch < 1) return fail(TC_ERR_INVALID_ARG, "MLP sizes must be >= 1");
+  tc_mlp_s* n = new (std::nothrow) tc_mlp_s();
+  if (!n) return fail(TC_ERR_NOMEM, "host allocation failed");
+  n->d = tc::MlpDims{n_in, hidden, n_out};
+  n->max_batch = max_batch;
+  if (n->init() != hipSuccess) {
+    delete n;
+    return fail(TC_ERR_NOMEM, "MLP device buffers");
+  }
+  *out = n;
+  return TC_OK;
+}
+
+tc_status tc_mlp_num_params(tc_mlp_t mlp, int64_t* n) {
+  if (!mlp || !n) return fail(TC_ERR_INVALID_ARG, "null argument");
+  *n = mlp->d.num_params();
+  return TC_OK;
+}
+
+tc_status tc_mlp_set_params(tc_mlp_t mlp, const float* host_params) {
+  if (!mlp || !host_params) return fail(TC_ERR_INVALID_ARG, "null argument");
+  hipError_t e = hipMemcpy(mlp->params, host_params, mlp->d.num_params() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "MLP parameter upload");
+  mlp->step = 0;
+  const size_t bytes = mlp->d.num_params() * sizeof(float);
+  if ((e = hipMemset(mlp->m, 0, bytes)) != hipSuccess || (e = hipMemset(mlp->v, 0, bytes)) != hipSuccess)
+    return hip_fail(e, "MLP moment reset");
+  return TC_OK;
+}
+
+tc_status tc_mlp_get_params(tc_mlp_t mlp, float* host_params) {
+  if (!mlp || !host_params) return fail(TC_ERR_INVALID_ARG, "null argument");
+  hipError_t e = hipMemcpy(host_params, mlp->params, mlp->d.num_params() * sizeof(float), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? TC_OK : hip_fail(e, "MLP parameter download");
+}
+
+tc_status tc_mlp_forward(tc_mlp_t mlp, const float* X, float* Y, int batch, void* stream) {
+  if (!mlp || !X || !Y) return fail(TC_ERR_INVALID_ARG, "null argument");
+  if (batch < 0 || batch > mlp->max_batch) return fail(TC_ERR_INVALID_ARG, "batch exceeds max_batch");
+  hipError_t e = tc::mlp_forward(mlp->d, mlp->params, X, mlp->w.H1, mlp->w.H2, Y, batch, (hipStream_t)stream);
+  return e == hipSuccess ? TC_OK : hip_fail(e, "MLP forward");
+}
+
+tc_status tc_mlp_loss_grad(tc_mlp_t mlp, const float* X, const float* T, const float* M, int batch, float* grads,
+                           float* loss, void* stream) {
+  if (!mlp || !X || !T || !M) return fail(TC_ERR_INVALID_ARG, "null argument");
+  if (batch < 1 || batch > mlp->max_batch) return fail(TC_ERR_INVALID_ARG, "batch outside 1..max_batch");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = tc::mlp_forward(mlp->d, mlp->params, X, mlp->w.H1, mlp->w.H2, mlp->w.Y, batch, st);
+  if (e == hipSuccess) e = tc::mlp_backward(mlp->d, mlp->params, X, T, M, mlp->w, mlp->grads, mlp->sums, batch, st);
+  if (e == hipSuccess && grads)
+    e = hipMemcpyAsync(grads, mlp->grads, mlp->d.num_params() * sizeof(float), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, mlp->sums, sizeof(float), hipMemcpyDeviceToDevice, st);
+  return e == hipSuccess ? TC_OK : hip_fail(e, "MLP loss/gradient");
+}
+
+tc_status tc_mlp_train_step(tc_mlp_t mlp, const float* X, const float* T, const float* M, int batch, float lr,
+                            float* loss, void* stream) {
+  tc_status s = tc_mlp_loss_grad(mlp, X, T, M, batch, nullptr, loss, stream);
+  if (s != TC_OK) return s;
+  mlp->step++;
+  hipError_t e = tc::mlp_adam(mlp->params, mlp->grads, mlp->m, mlp->v, mlp->d.num_params(), lr, mlp->step,
+                              (hipStream_t)stream);
+  return e == hipSuccess ? TC_OK : hip_fail(e, "MLP Adam step");
+}
+
+tc_status tc_mlp_destroy(tc_mlp_t mlp) {
+  delete mlp;
   return TC_OK;
 }
 

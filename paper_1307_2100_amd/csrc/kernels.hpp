@@ -245,6 +245,25 @@ struct BatchLaunch {
 size_t batch_lds_bytes(int config, int slab_lds_doubles);
 hipError_t launch_batch(const BatchLaunch& bl, hipStream_t s);
 
+// The picker's MLP (n_in -> hidden -> hidden -> n_out, ReLU, FP32).
+struct MlpDims {
+  int n_in, hidden, n_out;
+  int64_t num_params() const {
+    return (int64_t)n_in * hidden + hidden + (int64_t)hidden * hidden + hidden + (int64_t)hidden * n_out + n_out;
+  }
+};
+struct MlpScratch {  // activations and their gradients for one batch
+  float *H1, *H2, *Y, *dY, *dH2, *dH1;
+};
+hipError_t mlp_forward(const MlpDims& d, const float* params, const float* X, float* H1, float* H2, float* Y, int B,
+                       hipStream_t s);
+// After mlp_forward into w.H1/w.H2/w.Y: gradients of the masked mean-squared
+// error into grads (same layout as params); sums[0] receives the loss.
+hipError_t mlp_backward(const MlpDims& d, const float* params, const float* X, const float* T, const float* M,
+                        const MlpScratch& w, float* grads, float* sums, int B, hipStream_t s);
+hipError_t mlp_adam(float* params, const float* grads, float* m, float* v, int64_t n, float lr, int step,
+                    hipStream_t s);
+
 // Y[sum idx_i sy_i] = X[sum idx_i sx_i] over all multi-indices.
 struct PermuteParams {
   const double* X;

@@ -23,6 +23,7 @@
 #include <tuple>
 #include <vector>
 #include <climits>
+#include <cmath>
 
 namespace tc {
 namespace {
@@ -192,6 +193,52 @@ void build_slabs(Analysis& an) {
 
 }  // namespace
 
+void picker_features(const Analysis& an, const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, float* f) {
+  const tc_plan_info& in = an.info;
+  const Group* G = an.g;
+  auto lg = [](double x) { return (float)std::log2(x < 1.0 ? 1.0 : x); };
+  for (int i = 0; i < TC_PICKER_FEATURES; ++i) f[i] = 0.f;
+  const double M = (double)in.M, N = (double)in.N, K = (double)in.K, L = (double)in.L;
+  f[0] = lg(M);
+  f[1] = lg(N);
+  f[2] = lg(K);
+  f[3] = lg(L);
+  f[4] = (float)in.nM;
+  f[5] = (float)in.nN;
+  f[6] = (float)in.nK;
+  f[7] = (float)in.nL;
+  f[8] = (float)A.rank;
+  f[9] = (float)B.rank;
+  f[10] = (float)C.rank;
+  const int cls[5] = {0, 1, 2, 31, 32};
+  for (int i = 0; i < 5; ++i) f[11 + i] = in.paper_class == cls[i] ? 1.f : 0.f;
+  f[16] = an.a_mfast ? 1.f : 0.f;
+  f[17] = an.a_kfast ? 1.f : 0.f;
+  f[18] = an.b_nfast ? 1.f : 0.f;
+  f[19] = an.b_kfast ? 1.f : 0.f;
+  f[20] = G[GN].n > 0 && G[GN].str[SC][0] == 1 ? 1.f : 0.f;
+  f[21] = (float)in.swapped;
+  f[22] = G[GM].n > 0 ? lg((double)G[GM].ext[0]) : 0.f;
+  f[23] = G[GN].n > 0 ? lg((double)G[GN].ext[0]) : 0.f;
+  f[24] = G[GK].n > 0 ? lg((double)G[GK].ext[0]) : 0.f;
+  f[25] = lg((double)an.elems[SA]);
+  f[26] = lg((double)an.elems[SB]);
+  f[27] = lg((double)an.elems[SC]);
+  f[28] = lg(in.flops);
+  f[29] = lg(in.bytes);
+  f[30] = in.bytes > 0 ? (float)std::log2(std::max(1e-3, in.flops / in.bytes)) : 0.f;
+  f[31] = lg(std::min(M, N));
+}
+
+int candidate_of(const Analysis& an) {
+  for (int c = 0; c < TC_PICKER_CANDIDATES - 1; ++c) {
+    if (kCandidates[c].recipe != an.info.recipe) continue;
+    if (an.kernel == Analysis::KERNEL_BATCHED || an.kernel == Analysis::KERNEL_SPLIT) return -1;
+    if (kCandidates[c].tile < 0 || kCandidates[c].tile == an.info.tile_id) return c;
+  }
+  return -1;
+}
+
 int paper_class(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, int unitA, int unitB) {
   int p = 0, batchA = 0, batchB = 0;
   auto is_batch = [&](int32_t l) { return find_label(A, l) >= 0 && find_label(B, l) >= 0 && find_label(C, l) >= 0; };
@@ -282,6 +329,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
   info.copy_operand = -1;
   info.tile_id = -1;
   info.k_split = 1;
+  info.picked_candidate = -1;
   info.unit_a = unit_mode(A0);
   info.unit_b = unit_mode(B0);
   info.unit_c = unit_mode(C0);

@@ -91,6 +91,23 @@ struct Analysis {
 tc_status analyze(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, const tc_options& opt,
                   Analysis* out, std::string* err);
 
+// Picker features of an analysis (TC_PICKER_FEATURES floats).
+void picker_features(const Analysis& an, const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, float* f);
+
+// The picker's candidates: (recipe, GEMM tile).
+struct Candidate {
+  tc_recipe recipe;
+  int tile;
+};
+constexpr Candidate kCandidates[TC_PICKER_CANDIDATES] = {
+    {TC_RECIPE_GEMM, 8},       {TC_RECIPE_GEMM, 14},      {TC_RECIPE_GEMM, 1},       {TC_RECIPE_GEMM, 9},
+    {TC_RECIPE_GEMM, 11},      {TC_RECIPE_GEMM, 12},      {TC_RECIPE_COPY_GEMM, 8},  {TC_RECIPE_COPY_GEMM, 1},
+    {TC_RECIPE_COPY_GEMM, 9},  {TC_RECIPE_COPY_GEMM, 11}, {TC_RECIPE_COPY_GEMM, 12}, {TC_RECIPE_GEMV, -1},
+    {TC_RECIPE_DOT, -1},       {TC_RECIPE_GER, -1},       {TC_RECIPE_AUTO, -1}};
+// The first candidate of the explicit table (not the last, TC_RECIPE_AUTO)
+// that an analysis corresponds to (-1 if none).
+int candidate_of(const Analysis& an);
+
 // The paper's class (0, 1, 2, 31, 32) from labels and stride-1 positions of
 // the two inputs after normalisation (exposed for tests through tc_analyze).
 int paper_class(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, int unitA, int unitB);

@@ -1,0 +1,168 @@
+"""Learned/tuned picker on the GPU: the plan follows the installed model or
+the tune cache, results never depend on the pick, and the trained model's
+picks are timed against the rules and against exhaustive timing."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_util import FP64_TOL, colmajor_zeros, componentwise_error, reference, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1307_2100_amd as tc  # noqa: E402
+from paper_1307_2100_amd import picker  # noqa: E402
+
+NP = 32 * 64 + 64 + 64 * 64 + 64 + 64 * tc.PICKER_CANDIDATES + tc.PICKER_CANDIDATES
+
+
+def _constant_model(order):
+    """A network whose output is the bias b2 alone: candidates ranked by `order`."""
+    params = np.zeros(NP, dtype=np.float32)
+    b2 = np.full(tc.PICKER_CANDIDATES, 100.0, dtype=np.float32)
+    for rank, c in enumerate(order):
+        b2[c] = rank
+    params[-tc.PICKER_CANDIDATES:] = b2
+    return params
+
+
+CASES = [
+    ("abcd", "cdij", "abij", {"a": 33, "b": 20, "c": 9, "d": 17, "i": 21, "j": 5}),    # class 1
+    ("akic", "kbcj", "abij", {"a": 19, "k": 7, "i": 6, "c": 23, "b": 17, "j": 8}),     # needs a permute
+    ("ik", "k", "i", {"i": 301, "k": 77}),                                             # matrix-vector
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_results_do_not_depend_on_the_pick(case):
+    la, lb, lc, ext = CASES[case]
+    A, B = synth.make_operands(900 + case, la, lb, ext)
+    ref, scale = reference(A, la, B, lb, lc)
+    dA, dB = to_dev(A), to_dev(B)
+    C = colmajor_zeros([ext[l] for l in lc])
+    legal = []
+    for c in range(tc.PICKER_CANDIDATES):
+        recipe, tile = tc.tc_picker_candidate(c)
+        try:
+            tc.Plan.for_tensors(dA, la, dB, lb, C, lc, recipe=recipe, tile_id=tile).close()
+            legal.append(c)
+        except tc.TCError:
+            pass
+    assert tc.PICKER_CANDIDATES - 1 in legal
+    taken = set()
+    try:
+        for c in range(tc.PICKER_CANDIDATES):
+            tc.tc_picker_install(_constant_model([c]), 64, np.zeros(32), np.ones(32))
+            C = colmajor_zeros([ext[l] for l in lc])
+            plan = tc.Plan.for_tensors(dA, la, dB, lb, C, lc, picker="mlp")
+            got = plan.info.picked_candidate
+            # the model's first choice when the shape can take it, else the next in its order
+            order = [c] + [x for x in range(tc.PICKER_CANDIDATES) if x != c]
+            assert got == next(x for x in order if x in legal), (c, got, legal)
+            taken.add(got)
+            plan.execute(dA, dB, C)
+            torch.cuda.synchronize()
+            assert componentwise_error(C.cpu().numpy(), ref, scale) <= FP64_TOL, (c, got)
+            plan.close()
+    finally:
+        tc.tc_picker_uninstall()
+    assert len(taken) >= 3
+    # without a model, picker="mlp" is the rules
+    C = colmajor_zeros([ext[l] for l in lc])
+    plan = tc.Plan.for_tensors(dA, la, dB, lb, C, lc, picker="mlp")
+    assert plan.info.picked_candidate == -1
+    plan.close()
+
+
+def test_tune_cache_round_trip(tmp_path):
+    la, lb, lc, ext = CASES[1]
+    A, B = synth.make_operands(950, la, lb, ext)
+    dA, dB = to_dev(A), to_dev(B)
+    C = colmajor_zeros([ext[l] for l in lc])
+    plan = tc.Plan.for_tensors(dA, la, dB, lb, C, lc)
+    best, best_ms, per = plan.autotune(dA, dB, C)
+    plan.close()
+    assert best_ms > 0 and per[best] == pytest.approx(best_ms)
+    assert all(t == -1 or t >= best_ms for t in per)
+    assert per[tc.PICKER_CANDIDATES - 1] > 0      # the rules' own plan always runs
+    tuned = tc.Plan.for_tensors(dA, la, dB, lb, C, lc, picker="tuned")
+    assert tuned.info.picked_candidate == best
+    tuned.execute(dA, dB, C)
+    torch.cuda.synchronize()
+    ref, scale = reference(A, la, B, lb, lc)
+    assert componentwise_error(C.cpu().numpy(), ref, scale) <= FP64_TOL
+    tuned.close()
+    path = str(tmp_path / "tune.txt")
+    tc.tc_tune_cache_save(path)
+    lines = open(path).read().split("\n")
+    mine = [ln for ln in lines if ln.strip()]
+    assert mine and all(ln.split()[0] == tc.tc_version() for ln in mine)
+    # another legal candidate for the same shape, and a stale line that must be ignored
+    other = next(c for c in range(tc.PICKER_CANDIDATES) if c != best and per[c] > 0)
+    sig = [ln for ln in mine if ln.split()[3] == str(best)][-1].split()
+    with open(path, "w") as f:
+        f.write(" ".join(sig[:3] + [str(other)]) + "\n")
+        f.write(" ".join(["0.0.0"] + sig[1:3] + [str(best)]) + "\n")
+    tc.tc_tune_cache_load(path)
+    tuned = tc.Plan.for_tensors(dA, la, dB, lb, C, lc, picker="tuned")
+    assert tuned.info.picked_candidate == other
+    tuned.close()
+    with pytest.raises(tc.TCError):
+        tc.tc_tune_cache_load(str(tmp_path / "missing.txt"))
+
+
+def test_missing_or_corrupt_model_keeps_the_rules(tmp_path):
+    bad = tmp_path / "model.json"
+    bad.write_text('{"format": "tc-picker-mlp", "n_in": 3}')
+    assert picker.install(str(bad)) is False
+    assert picker.install(str(tmp_path / "none.json")) is False
+    la, lb, lc, ext = CASES[0]
+    A, B = synth.make_operands(960, la, lb, ext)
+    dA, dB = to_dev(A), to_dev(B)
+    C = colmajor_zeros([ext[l] for l in lc])
+    plan = tc.Plan.for_tensors(dA, la, dB, lb, C, lc, picker="mlp")
+    assert plan.info.picked_candidate == -1
+    plan.close()
+
+
+@pytest.mark.skipif(not os.path.exists(picker.DEFAULT_MODEL), reason="no trained picker model in the package")
+def test_trained_model_against_rules_and_exhaustive_timing():
+    """Fresh random shapes (a seed the model was not trained on), every
+    candidate timed; the installed model's picks made by tc_plan_create."""
+    assert picker.install()
+    n, rows, picked = 64, [], []
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(12345)
+    try:
+        for i in range(n):
+            shape = picker.random_shape(np.random.default_rng([777, i]))
+            dA, dB, dC = picker._descs(shape)
+            A = picker._alloc(torch, shape["a"], gen)
+            B = picker._alloc(torch, shape["b"], gen)
+            C = picker._alloc(torch, shape["c"], gen)
+            plan = tc.Plan(dA, dB, dC)
+            _, _, per = plan.autotune(A, B, C)
+            plan.close()
+            mlp = tc.Plan(dA, dB, dC, picker="mlp")
+            picked.append(mlp.info.picked_candidate)
+            mlp.close()
+            rows.append(per)
+    finally:
+        tc.tc_picker_uninstall()
+    ms = np.array([[t if t > 0 else np.nan for t in r] for r in rows])
+    pick = np.array(picked)
+    assert np.all(pick >= 0) and np.all(np.isfinite(ms[np.arange(n), pick]))
+    best = np.nanmin(ms, axis=1)
+    t_pick = ms[np.arange(n), pick]
+    t_rule = ms[:, tc.PICKER_CANDIDATES - 1]
+    gm = lambda x: float(np.exp(np.mean(np.log(x))))  # noqa: E731
+    res = dict(pick_over_best=gm(t_pick / best), rules_over_best=gm(t_rule / best), gain=gm(t_rule / t_pick))
+    print("picker on fresh shapes:", res)
+    # the network must not lose to the rules it augments
+    assert res["gain"] >= 1.0
