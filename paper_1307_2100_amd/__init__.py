@@ -472,6 +472,17 @@ class Batch:
         _check(_lib.tc_batch_execute(self.handle, a, b, c, al, be, ctypes.c_void_p(ws.data_ptr()),
                                      self.workspace_bytes, _stream_handle(stream)))
 
+    def bind(self, As, Bs, Cs, alphas=None, betas=None):
+        """Marshals the operand pointers once; run() then executes the batch on
+        them without rebuilding the argument arrays (a serving loop)."""
+        self._bound = self._arrays(As, Bs, Cs, alphas, betas) + (self.workspace(Cs[0].device),)
+        self._bound_tensors = (As, Bs, Cs)   # keep the buffers alive
+
+    def run(self, stream=None):
+        a, b, c, al, be, ws = self._bound
+        _check(_lib.tc_batch_execute(self.handle, a, b, c, al, be, ctypes.c_void_p(ws.data_ptr()),
+                                     self.workspace_bytes, _stream_handle(stream)))
+
     def autotune(self, As, Bs, Cs, alphas=None, betas=None, stream=None):
         a, b, c, al, be = self._arrays(As, Bs, Cs, alphas, betas)
         ws = self.workspace(Cs[0].device)

@@ -118,6 +118,72 @@ tc_status upload_tables(const std::vector<int64_t>& host, const std::vector<std:
   return TC_OK;
 }
 
+// Slab-engine parameters of a batch-dominated contraction: the operands'
+// slab descriptors, the per-index LDS offset tables (appended to `host`), the
+// points per workgroup for `lds_doubles` of LDS and the fast divisors.  The
+// batch offsets bp.aL, bp.bL, bp.cL must already be set by build_tables.
+tc_status fill_slab(const tc::Analysis& an, tc::BatchedParams& bp, int lds_doubles, std::vector<int64_t>& host,
+                    std::vector<std::pair<tc::Offs*, size_t>>& pos) {
+  const tc::Group* G = an.g;
+  const tc_plan_info& info = an.info;
+  tc::SlabDesc* d[3] = {&bp.a, &bp.b, &bp.c};
+  const tc::Offs* xl[3] = {&bp.aL, &bp.bL, &bp.cL};
+  for (int slot = 0; slot < 3; ++slot) {
+    tc::SlabDesc& sd = *d[slot];
+    sd.n = an.slab_n[slot];
+    sd.size = an.slab_size[slot];
+    sd.size_div = tc::make_fastdiv((uint32_t)an.slab_size[slot]);
+    sd.batch_fast = an.slab_batch_fast[slot];
+    sd.dense = an.slab_dense[slot];
+    sd.s0 = an.slab_s0[slot];
+    // contiguous: dense with unit stride and the batch offset an affine step of one slab
+    sd.contig = sd.dense && !sd.batch_fast && sd.s0 == 1 && xl[slot]->tab == nullptr &&
+                        xl[slot]->stride == (int64_t)sd.size && G[tc::GL].n <= 1
+                    ? 1
+                    : 0;
+    for (int i = 0; i < an.slab_n[slot]; ++i) {
+      sd.div[i] = tc::make_fastdiv((uint32_t)an.slab_ext[slot][i]);
+      sd.gstr[i] = an.slab_gstr[slot][i];
+      sd.lstr[i] = an.slab_lstr[slot][i];
+    }
+  }
+  // LDS offset tables: (slot, group, offsets, canonical weight of the group's linear index)
+  struct Want {
+    int slot, group;
+    tc::Offs* dst;
+    int64_t canon;
+  } want[6] = {{tc::SA, tc::GM, &bp.am, info.K}, {tc::SA, tc::GK, &bp.ak, 1},
+               {tc::SB, tc::GN, &bp.bn, info.K}, {tc::SB, tc::GK, &bp.bk, 1},
+               {tc::SC, tc::GM, &bp.cm, info.N}, {tc::SC, tc::GN, &bp.cn, 1}};
+  for (const Want& w : want) {
+    const tc::Group& g = G[w.group];
+    *w.dst = tc::Offs{};
+    if (!an.slab_dense[w.slot]) {
+      w.dst->stride = w.canon;
+      continue;
+    }
+    const int64_t s0 = an.slab_s0[w.slot];
+    if (g.n <= 1) {
+      w.dst->stride = g.n == 1 ? g.str[w.slot][0] / s0 : 0;
+      continue;
+    }
+    pos.push_back({w.dst, host.size()});
+    for (int64_t i = 0; i < g.size(); ++i) host.push_back(g.offset(w.slot, i) / s0);
+  }
+  const int per = an.slab_size[0] + an.slab_size[1] + an.slab_size[2];
+  const int P = tc::slab_points(per, (int)info.K, lds_doubles);
+  if (P < 1) return fail(TC_ERR_UNSUPPORTED, "per-point slabs do not fit the workgroup's LDS");
+  bp.P = P;
+  bp.M = (int)info.M;
+  bp.N = (int)info.N;
+  bp.K = (int)info.K;
+  bp.L = info.L;
+  bp.P_div = tc::make_fastdiv((uint32_t)P);
+  bp.N_div = tc::make_fastdiv((uint32_t)bp.N);
+  bp.sC_div = tc::make_fastdiv((uint32_t)bp.c.size);
+  return TC_OK;
+}
+
 }  // namespace
 
 struct tc_plan_s {
@@ -128,6 +194,7 @@ struct tc_plan_s {
   int64_t* d_tables = nullptr;
   // per-group offsets of each kernel operand (A: M,K,L; B: N,K,L; C: M,N,L)
   tc::Offs aM{}, aK{}, aL{}, bN{}, bK{}, bL{}, cM{}, cN{}, cL{};
+  tc::BatchedParams slab{};  // slab-engine layout (batch-dominated plans)
 };
 
 // The picker's network on the device: parameters, Adam moments, gradients
@@ -258,6 +325,7 @@ struct tc_batch_s {
   hipStream_t capture_stream = nullptr;
   hipEvent_t done = nullptr;
   bool done_recorded = false;
+  bool staged = false;  // h_ptrs holds the pointers of the last execution
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void* graph_ws = nullptr;
@@ -282,15 +350,15 @@ struct tc_batch_s {
     graph_ws = nullptr;
   }
 
-  // workspace: [pointers][task counter][tile counters][partial tiles]
-  int64_t n_cnt = 0;      // split tiles of the current configuration
-  int64_t n_parts = 0;    // partial tiles of the current configuration
+  // workspace: [pointers][task counter][completion counters][partial sums]
+  int64_t n_cnt = 0;      // completion counters of the current configuration
+  int64_t n_parts = 0;    // partial sums (doubles) of the current configuration
   size_t max_ws = 0;      // largest workspace over all configurations
   size_t ptrs_bytes() const { return ((size_t)n * sizeof(tc::BatchPtrs) + 255) / 256 * 256; }
   size_t cnt_offset() const { return ptrs_bytes() + 256; }
   size_t parts_offset(int64_t ncnt) const { return cnt_offset() + ((size_t)ncnt * 4 + 255) / 256 * 256; }
-  size_t workspace_for(int64_t ncnt, int64_t nparts, int cfg) const {
-    return parts_offset(ncnt) + (size_t)nparts * tc::kBatchTileBM[cfg] * tc::kBatchTileBN[cfg] * sizeof(double);
+  size_t workspace_for(int64_t ncnt, int64_t nparts) const {
+    return parts_offset(ncnt) + (size_t)nparts * sizeof(double);
   }
   size_t workspace_bytes() const { return max_ws; }
 
@@ -321,7 +389,31 @@ struct tc_batch_s {
     n_parts = 0;
     for (int i = 0; i < n; ++i) {
       tc::BatchItem& it = items[i];
-      if (it.kind == 0) {
+      if (it.kind == tc::kBatchLanesK || it.kind == tc::kBatchLanesOut) {
+        // memory-bound: groups of outputs; long contracted ranges in segments
+        const bool lk = it.kind == tc::kBatchLanesK;
+        const int64_t outputs = it.g.M * it.g.N * it.g.L;
+        const int64_t per = lk ? tc::kLanesKOutputs : tc::kLanesOutOutputs;
+        const int64_t groups = (outputs + per - 1) / per;
+        const int64_t target = lk ? 16384 : 512;  // contracted indices per segment
+        int S = 1;
+        int64_t len = it.g.K;
+        if (it.g.K > 2 * target) {
+          S = (int)((it.g.K + target - 1) / target);
+          len = (it.g.K + S - 1) / S;
+        }
+        it.ksplit = S;
+        it.seg_len = len;
+        it.part_off = S > 1 ? n_parts : 0;
+        it.cnt_off = S > 1 ? n_cnt : 0;
+        if (S > 1) {
+          n_parts += outputs * S;
+          n_cnt += groups;
+        }
+        const double cost = 16.0 * (double)per * (double)len / 8e12;
+        for (int64_t t = 0; t < groups; ++t)
+          for (int sg = 0; sg < S; ++sg) tasks.push_back({cost, tc::BatchTask{i, sg, t}});
+      } else if (it.kind == tc::kBatchGemm) {
         it.tilesM = (it.g.M + BM - 1) / BM;
         it.tilesN = (it.g.N + BN - 1) / BN;
         const int64_t nt = it.tilesM * it.tilesN * it.g.L;
@@ -333,7 +425,7 @@ struct tc_batch_s {
         it.part_off = S > 1 ? n_parts : 0;
         it.cnt_off = S > 1 ? n_cnt : 0;
         if (S > 1) {
-          n_parts += nt * S;
+          n_parts += nt * S * BM * BN;
           n_cnt += nt;
         }
         // cost of a task: the larger of its FP64 MFMA time and its load time
@@ -407,7 +499,7 @@ struct tc_batch_s {
   tc_status execute(const double* const* A, const double* const* B, double* const* C, const double* alpha,
                     const double* beta, void* ws, size_t wsb, hipStream_t st, int graph_on) {
     if (!A || !B || !C || !alpha || !beta) return fail(TC_ERR_INVALID_ARG, "null pointer array");
-    if (!ws || wsb < workspace_for(n_cnt, n_parts, config))
+    if (!ws || wsb < workspace_for(n_cnt, n_parts))
       return fail(TC_ERR_WORKSPACE, "batch workspace of " + std::to_string(wsb) + " bytes, needs " +
                                         std::to_string(workspace_bytes()));
     int dev = -1;
@@ -417,9 +509,19 @@ struct tc_batch_s {
       if (analyses[i].M * analyses[i].N * analyses[i].L > 0 && !C[i])
         return fail(TC_ERR_INVALID_ARG, "null C in batch entry " + std::to_string(i));
     }
-    // the previous execution must have consumed the pinned staging buffer
-    if (done_recorded && hipEventSynchronize(done) != hipSuccess) return fail(TC_ERR_HIP, "batch event sync");
-    for (int i = 0; i < n; ++i) h_ptrs[i] = tc::BatchPtrs{A[i], B[i], C[i], alpha[i], beta[i]};
+    // New pointers or scalars go through the pinned staging buffer, which the
+    // previous execution must have consumed first.  Unchanged ones (the usual
+    // serving loop over the same buffers) are already staged: no wait.
+    bool same = staged;
+    for (int i = 0; i < n && same; ++i) {
+      const tc::BatchPtrs v{A[i], B[i], C[i], alpha[i], beta[i]};
+      same = std::memcmp(&v, &h_ptrs[i], sizeof(v)) == 0;
+    }
+    if (!same) {
+      if (done_recorded && hipEventSynchronize(done) != hipSuccess) return fail(TC_ERR_HIP, "batch event sync");
+      for (int i = 0; i < n; ++i) h_ptrs[i] = tc::BatchPtrs{A[i], B[i], C[i], alpha[i], beta[i]};
+      staged = true;
+    }
     hipError_t e;
     if (graph_on) {
       if (!exec || graph_ws != ws) {
@@ -517,10 +619,26 @@ tc_status tc_plan_create(tc_plan_t* out, int ra, const int64_t* ea, const int64_
   std::vector<std::pair<tc::Offs*, size_t>> pos;
   build_tables(p->an, OffsTargets{&p->aM, &p->aK, &p->aL, &p->bN, &p->bK, &p->bL, &p->cM, &p->cN, &p->cL}, host,
                pos);
+  const bool slab = p->an.kernel == tc::Analysis::KERNEL_BATCHED;
+  if (slab) {
+    p->slab.aL = p->aL;
+    p->slab.bL = p->bL;
+    p->slab.cL = p->cL;
+    s = fill_slab(p->an, p->slab, tc::kBatchedLdsDoubles, host, pos);
+    if (s != TC_OK) {
+      delete p;
+      return s;
+    }
+  }
   s = upload_tables(host, pos, &p->d_tables);
   if (s != TC_OK) {
     delete p;
     return s;
+  }
+  if (slab) {  // the batch offsets as uploaded
+    p->slab.aL = p->aL;
+    p->slab.bL = p->bL;
+    p->slab.cL = p->cL;
   }
   *out = p;
   return TC_OK;
@@ -636,33 +754,10 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
   gp.alpha = alpha;
   gp.beta = beta;
   if (an.kernel == tc::Analysis::KERNEL_BATCHED) {
-    tc::BatchedParams bp{};
+    tc::BatchedParams bp = plan->slab;
     bp.A = KA;
     bp.B = KB;
     bp.C = C;
-    bp.aL = plan->aL;
-    bp.bL = plan->bL;
-    bp.cL = plan->cL;
-    tc::SlabDesc* d[3] = {&bp.a, &bp.b, &bp.c};
-    for (int slot = 0; slot < 3; ++slot) {
-      d[slot]->n = an.slab_n[slot];
-      d[slot]->size = an.slab_size[slot];
-      d[slot]->size_div = tc::make_fastdiv((uint32_t)an.slab_size[slot]);
-      d[slot]->batch_fast = an.slab_batch_fast[slot];
-      for (int i = 0; i < an.slab_n[slot]; ++i) {
-        d[slot]->div[i] = tc::make_fastdiv((uint32_t)an.slab_ext[slot][i]);
-        d[slot]->gstr[i] = an.slab_gstr[slot][i];
-        d[slot]->lstr[i] = an.slab_lstr[slot][i];
-      }
-    }
-    bp.M = (int)info.M;
-    bp.N = (int)info.N;
-    bp.K = (int)info.K;
-    bp.P = an.batched_P;
-    bp.P_div = tc::make_fastdiv((uint32_t)bp.P);
-    bp.N_div = tc::make_fastdiv((uint32_t)bp.N);
-    bp.sC_div = tc::make_fastdiv((uint32_t)bp.c.size);
-    bp.L = info.L;
     bp.alpha = alpha;
     bp.beta = beta;
     e = tc::launch_batched_small(bp, s);
@@ -763,15 +858,18 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
       delete b;
       return fail(TC_ERR_INVALID_ARG, "plans of a batch must share the current device");
     }
-    // Re-plan for the batch's two engines: batch-dominated contractions keep
-    // the slab engine, everything else runs as direct GEMM tiles (a batch has
-    // no per-contraction copy or memory-bound kernels).
+    // Re-plan for the batch's engines: batch-dominated contractions keep the
+    // slab engine, the memory-bound matrix-vector and inner-product shapes
+    // their lanes kernels, everything else runs as direct GEMM tiles (a batch
+    // has no per-contraction copy pass).
     tc_options o = p->opt;
     o.recipe = TC_RECIPE_AUTO;
     tc::Analysis an;
     std::string err;
     tc_status s = tc::analyze(p->desc[0], p->desc[1], p->desc[2], o, &an, &err);
-    if (s == TC_OK && an.kernel != tc::Analysis::KERNEL_BATCHED) {
+    const bool keep = an.kernel == tc::Analysis::KERNEL_BATCHED || an.kernel == tc::Analysis::KERNEL_LANES_K ||
+                      an.kernel == tc::Analysis::KERNEL_LANES_OUT;
+    if (s == TC_OK && !keep) {
       o.recipe = TC_RECIPE_GEMM;
       s = tc::analyze(p->desc[0], p->desc[1], p->desc[2], o, &an, &err);
     }
@@ -787,35 +885,16 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
       build_tables(an, OffsTargets{&it.g.aM, &it.g.aK, &it.b.aL, &it.g.bN, &it.g.bK, &it.b.bL, &it.g.cM, &it.g.cN,
                                    &it.b.cL},
                    host, pos);
-      tc::SlabDesc* d[3] = {&it.b.a, &it.b.b, &it.b.c};
-      for (int slot = 0; slot < 3; ++slot) {
-        d[slot]->n = an.slab_n[slot];
-        d[slot]->size = an.slab_size[slot];
-        d[slot]->size_div = tc::make_fastdiv((uint32_t)an.slab_size[slot]);
-        d[slot]->batch_fast = an.slab_batch_fast[slot];
-        for (int q = 0; q < an.slab_n[slot]; ++q) {
-          d[slot]->div[q] = tc::make_fastdiv((uint32_t)an.slab_ext[slot][q]);
-          d[slot]->gstr[q] = an.slab_gstr[slot][q];
-          d[slot]->lstr[q] = an.slab_lstr[slot][q];
-        }
-      }
-      const int per = an.slab_size[0] + an.slab_size[1] + an.slab_size[2];
-      int P = tc::kBatchSlabLdsDoubles / per;
-      if (P > 64) P = 64;
-      if (P < 1) {
+      s = fill_slab(an, it.b, tc::kBatchSlabLdsDoubles, host, pos);
+      if (s != TC_OK) {
         delete b;
-        return fail(TC_ERR_UNSUPPORTED, "batch slab too large");
+        return s;
       }
-      it.b.P = P;
-      it.b.M = (int)an.info.M;
-      it.b.N = (int)an.info.N;
-      it.b.K = (int)an.info.K;
-      it.b.L = an.info.L;
-      it.b.P_div = tc::make_fastdiv((uint32_t)P);
-      it.b.N_div = tc::make_fastdiv((uint32_t)it.b.N);
-      it.b.sC_div = tc::make_fastdiv((uint32_t)it.b.c.size);
     } else {
-      it.kind = 0;
+      it.kind = an.kernel == tc::Analysis::KERNEL_LANES_K     ? tc::kBatchLanesK
+                : an.kernel == tc::Analysis::KERNEL_LANES_OUT ? tc::kBatchLanesOut
+                                                              : tc::kBatchGemm;
+      it.n_fastest = an.n_fastest ? 1 : 0;
       build_tables(an, OffsTargets{&it.g.aM, &it.g.aK, &it.g.aL, &it.g.bN, &it.g.bK, &it.g.bL, &it.g.cM, &it.g.cN,
                                    &it.g.cL},
                    host, pos);
@@ -852,7 +931,7 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
       delete b;
       return s;
     }
-    b->max_ws = std::max(b->max_ws, b->workspace_for(b->n_cnt, b->n_parts, cfg));
+    b->max_ws = std::max(b->max_ws, b->workspace_for(b->n_cnt, b->n_parts));
   }
   *out = b;
   return TC_OK;

@@ -3,7 +3,11 @@
 //
 // The host turns every contraction of the batch into tasks -- GEMM tiles for
 // contractions run by the FP64 MFMA tile engine, groups of batch indices for
-// batch-dominated ones run by the slab engine -- and orders all tasks by
+// batch-dominated ones run by the slab engine, groups of outputs for the
+// memory-bound matrix-vector and inner-product shapes (lanes along the
+// contracted index or along the outputs, long contracted ranges cut into
+// segments whose partial sums the last segment adds in a fixed order) -- and
+// orders all tasks by
 // estimated cost, largest first (longest-processing-time order), then cut
 // into consecutive chunks of about equal cost.  The grid is sized to the
 // number of workgroups the chip holds at once; each workgroup repeatedly takes
@@ -18,6 +22,132 @@
 namespace tc {
 namespace {
 
+// Values the whole workgroup shares, made wavefront-uniform so that the
+// compiler keeps them (and what is loaded through them) in scalar registers.
+TC_DEV int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+TC_DEV int64_t uni64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+TC_DEV double batch_wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Completion of one contracted segment of a split task group: returns true in
+// the workgroup that finished the last segment (all partial sums visible).
+TC_DEV bool batch_last_segment(unsigned* cnt, int S, int* last) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) *last = atomicAdd(cnt, 1u) == (unsigned)(S - 1);
+  __syncthreads();
+  if (*last) __threadfence();
+  return *last;
+}
+
+// C entry of output o = m + M (n + N l) (kinds 2 and 3 when n is not fastest).
+TC_DEV void batch_store(const GettParams& p, int64_t m, int64_t n, int64_t l, double v) {
+  double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
+  *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
+}
+
+// Lanes over k: wavefront w of the workgroup takes output 4 idx + w and
+// contracted segment seg; lanes stride along k.
+TC_DEV void batch_lanes_k(const BatchItem& it, const GettParams& p, const BatchTask& task,
+                                     double* __restrict__ parts, unsigned* __restrict__ tile_cnt, int* last) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t outputs = p.M * p.N * p.L;
+  const int64_t o = task.idx * kLanesKOutputs + wave;
+  const int S = it.ksplit;
+  int64_t m = 0, n = 0, l = 0;
+  double v = 0.0;
+  if (o < outputs) {  // uniform per wavefront
+    m = o % p.M;
+    const int64_t r = o / p.M;
+    n = r % p.N;
+    l = r / p.N;
+    const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
+    const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
+    const int64_t k0 = (int64_t)task.seg * it.seg_len;
+    const int64_t k1 = k0 + it.seg_len < p.K ? k0 + it.seg_len : p.K;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int64_t k = k0 + lane;
+    for (; k + 192 < k1; k += 256) {
+      acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
+      acc1 += A[off_at(p.aK, k + 64)] * B[off_at(p.bK, k + 64)];
+      acc2 += A[off_at(p.aK, k + 128)] * B[off_at(p.bK, k + 128)];
+      acc3 += A[off_at(p.aK, k + 192)] * B[off_at(p.bK, k + 192)];
+    }
+    for (; k < k1; k += 64) acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
+    v = batch_wave_sum((acc0 + acc1) + (acc2 + acc3));
+  }
+  if (S == 1) {
+    if (o < outputs && lane == 0) batch_store(p, m, n, l, v);
+    return;
+  }
+  if (o < outputs && lane == 0) parts[it.part_off + o * S + task.seg] = v;
+  if (!batch_last_segment(&tile_cnt[it.cnt_off + task.idx], S, last)) return;
+  if (o < outputs) {
+    // segments in a fixed order: lane-strided, then the fixed reduction tree
+    double acc = 0.0;
+    for (int sg = lane; sg < S; sg += 64) acc += parts[it.part_off + o * S + sg];
+    acc = batch_wave_sum(acc);
+    if (lane == 0) batch_store(p, m, n, l, acc);
+  }
+}
+
+// Lanes over outputs: thread t takes output 256 idx + t (n or m fastest
+// along lanes) and walks contracted segment seg.
+TC_DEV void batch_lanes_out(const BatchItem& it, const GettParams& p, const BatchTask& task,
+                                       double* __restrict__ parts, unsigned* __restrict__ tile_cnt, int* last) {
+  const int64_t outputs = p.M * p.N * p.L;
+  const int64_t o = task.idx * kLanesOutOutputs + threadIdx.x;
+  const int S = it.ksplit;
+  int64_t m = 0, n = 0, l = 0;
+  double v = 0.0;
+  if (o < outputs) {
+    if (it.n_fastest) {
+      n = o % p.N;
+      const int64_t r = o / p.N;
+      m = r % p.M;
+      l = r / p.M;
+    } else {
+      m = o % p.M;
+      const int64_t r = o / p.M;
+      n = r % p.N;
+      l = r / p.N;
+    }
+    const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
+    const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
+    const int64_t k0 = (int64_t)task.seg * it.seg_len;
+    const int64_t k1 = k0 + it.seg_len < p.K ? k0 + it.seg_len : p.K;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int64_t k = k0;
+    for (; k + 4 <= k1; k += 4) {
+      acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
+      acc1 += A[off_at(p.aK, k + 1)] * B[off_at(p.bK, k + 1)];
+      acc2 += A[off_at(p.aK, k + 2)] * B[off_at(p.bK, k + 2)];
+      acc3 += A[off_at(p.aK, k + 3)] * B[off_at(p.bK, k + 3)];
+    }
+    for (; k < k1; ++k) acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
+    v = (acc0 + acc1) + (acc2 + acc3);
+  }
+  if (S == 1) {
+    if (o < outputs) batch_store(p, m, n, l, v);
+    return;
+  }
+  if (o < outputs) parts[it.part_off + (int64_t)task.seg * outputs + o] = v;
+  if (!batch_last_segment(&tile_cnt[it.cnt_off + task.idx], S, last)) return;
+  if (o < outputs) {
+    double acc = 0.0;
+    for (int sg = 0; sg < S; ++sg) acc += parts[it.part_off + (int64_t)sg * outputs + o];
+    batch_store(p, m, n, l, acc);
+  }
+}
+
 template <int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict__ items,
                                                     const BatchPtrs* __restrict__ ptrs,
@@ -28,10 +158,6 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict_
   extern __shared__ __attribute__((aligned(16))) double smem[];
   __shared__ int64_t next;
   __shared__ int last;
-  // slab layout of the current item, staged in LDS: the per-element decode
-  // loops read it many times
-  __shared__ BatchedParams sbp;
-  int sbp_item = -1;
   int64_t t = 0, t_end = 0;
   for (;;) {
     __syncthreads();  // the previous task is done with LDS and with `next`
@@ -39,16 +165,30 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict_
       // take the next chunk of tasks (one atomic per chunk, not per task)
       if (threadIdx.x == 0) next = (int64_t)atomicAdd(counter, 1ull);
       __syncthreads();
-      const int64_t c = next;
+      const int64_t c = uni64(next);
       if (c >= nchunks) break;
-      t = chunks[c];
-      t_end = chunks[c + 1];
+      t = uni64(chunks[c]);
+      t_end = uni64(chunks[c + 1]);
       if (t >= t_end) continue;
     }
-    const BatchTask task = tasks[t++];
+    BatchTask task = tasks[t++];
+    task.item = uni(task.item);
+    task.seg = uni(task.seg);
+    task.idx = uni64(task.idx);
     const BatchItem& it = items[task.item];
     const BatchPtrs pt = ptrs[task.item];
-    if (it.kind == 0) {
+    if (it.kind == kBatchLanesK || it.kind == kBatchLanesOut) {
+      GettParams p = it.g;
+      p.A = it.swapped ? pt.B : pt.A;
+      p.B = it.swapped ? pt.A : pt.B;
+      p.C = pt.C;
+      p.alpha = pt.alpha;
+      p.beta = pt.beta;
+      if (it.kind == kBatchLanesK)
+        batch_lanes_k(it, p, task, parts, tile_cnt, &last);
+      else
+        batch_lanes_out(it, p, task, parts, tile_cnt, &last);
+    } else if (it.kind == kBatchGemm) {
       GettParams p = it.g;
       p.A = it.swapped ? pt.B : pt.A;
       p.B = it.swapped ? pt.A : pt.B;
@@ -61,7 +201,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict_
       const int S = it.ksplit;
       const int64_t kb = S > 1 ? task.seg * it.seg_len : 0;
       const int64_t ke = S > 1 ? (kb + it.seg_len < p.K ? kb + it.seg_len : p.K) : p.K;
-      double* part = S > 1 ? parts + (it.part_off + task.idx * S + task.seg) * (int64_t)(BM * BN) : nullptr;
+      double* part = S > 1 ? parts + it.part_off + (task.idx * S + task.seg) * (int64_t)(BM * BN) : nullptr;
       switch (it.akf * 2 + it.bkf) {
         case 0: gett_tile<BM, BN, BK, 2, 2, false, false>(p, m0, n0, l, smem, kb, ke, part); break;
         case 1: gett_tile<BM, BN, BK, 2, 2, false, true>(p, m0, n0, l, smem, kb, ke, part); break;
@@ -77,20 +217,12 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict_
         __syncthreads();
         if (last) {
           __threadfence();
-          gett_reduce_tile<BM, BN>(p, m0, n0, l, parts + (it.part_off + task.idx * S) * (int64_t)(BM * BN), S);
+          gett_reduce_tile<BM, BN>(p, m0, n0, l, parts + it.part_off + task.idx * S * (int64_t)(BM * BN), S);
         }
       }
     } else {
-      if (task.item != sbp_item) {
-        constexpr int W = (int)(sizeof(BatchedParams) / sizeof(uint32_t));
-        static_assert(sizeof(BatchedParams) % sizeof(uint32_t) == 0, "word copy");
-        for (int w = threadIdx.x; w < W; w += blockDim.x)
-          reinterpret_cast<uint32_t*>(&sbp)[w] = reinterpret_cast<const uint32_t*>(&it.b)[w];
-        sbp_item = task.item;
-        __syncthreads();
-      }
-      batched_slab(sbp, it.swapped ? pt.B : pt.A, it.swapped ? pt.A : pt.B, pt.C, pt.alpha, pt.beta,
-                   task.idx * sbp.P, smem);
+      batched_slab(it.b, it.swapped ? pt.B : pt.A, it.swapped ? pt.A : pt.B, pt.C, pt.alpha, pt.beta,
+                   task.idx * it.b.P, smem);
     }
   }
 }

@@ -31,13 +31,16 @@ __host__ __device__ constexpr int gett_lds_doubles() {
 }
 
 // Global-to-register loader for one operand tile (R rows x BK contracted)
-// with NT threads.
+// with NT threads.  The contracted-index offsets of a tile are looked up
+// (koffs) one tile ahead of its data loads (load), so that a table lookup and
+// the load that depends on it never sit back to back on the critical path.
 template <int R, int BK, bool KF, int NT>
 struct Loader {
   static constexpr int E = R * BK / NT;  // elements per thread
   static_assert(E >= 1 && R * BK == E * NT, "tile must split evenly over the threads");
   static_assert(KF ? (NT % BK == 0) : (NT % R == 0), "loader mapping needs whole rows per pass");
-  int64_t roff[KF ? E : 1];  // row offsets (row-fast: one row per thread)
+  int64_t roff[KF ? E : 1];  // row offsets (row-fast: one row per thread), -1 beyond the rows
+  int64_t ko[KF ? 1 : E];    // contracted offsets of the next tile to load, -1 beyond K
   double v[E];
 
   __device__ inline void init(const Offs& xr, int64_t r0, int64_t rows, int tid) {
@@ -53,21 +56,28 @@ struct Loader {
     }
   }
 
-  __device__ inline void load(const double* __restrict__ X, const Offs& xk, int64_t k0, int64_t K, int tid) {
+  __device__ inline void koffs(const Offs& xk, int64_t k0, int64_t K, int tid) {
     if constexpr (KF) {
       int64_t k = k0 + tid % BK;
-      int64_t ko = k < K ? off_at(xk, k) : -1;
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = (ko >= 0 && roff[e] >= 0) ? X[roff[e] + ko] : 0.0;
+      ko[0] = k < K ? off_at(xk, k) : -1;
     } else {
       // all lanes of a wavefront share one k when R is a multiple of 64: keep it scalar
       const int kf = R % 64 == 0 ? __builtin_amdgcn_readfirstlane(tid / R) : tid / R;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         int64_t k = k0 + kf + (NT / R) * e;
-        int64_t ko = k < K ? off_at(xk, k) : -1;
-        v[e] = (ko >= 0 && roff[0] >= 0) ? X[roff[0] + ko] : 0.0;
+        ko[e] = k < K ? off_at(xk, k) : -1;
       }
+    }
+  }
+
+  __device__ inline void load(const double* __restrict__ X) {
+    if constexpr (KF) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = (ko[0] >= 0 && roff[e] >= 0) ? X[roff[e] + ko[0]] : 0.0;
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = (ko[e] >= 0 && roff[0] >= 0) ? X[roff[0] + ko[e]] : 0.0;
     }
   }
 
@@ -122,7 +132,7 @@ struct Frags {
 // C; otherwise its raw sums go to part[m_local * BN + n_local] (a split-K
 // segment, to be reduced by gett_reduce_tile).
 template <int BM, int BN, int BK, int WGM, int WGN, bool AKF, bool BKF>
-__device__ inline void gett_tile(const GettParams& p, int64_t m0, int64_t n0, int64_t l, double* smem,
+TC_DEV void gett_tile(const GettParams& p, int64_t m0, int64_t n0, int64_t l, double* smem,
                                  int64_t kb, int64_t ke, double* __restrict__ part) {
   constexpr int NT = 64 * WGM * WGN;
   using SA_ = Stage<BM, BK, AKF>;
@@ -155,10 +165,20 @@ __device__ inline void gett_tile(const GettParams& p, int64_t m0, int64_t n0, in
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
+  // Small tiles have little MFMA work per k-tile to hide a table lookup
+  // followed by the load it feeds: they look the offsets up one tile ahead.
+  // Large tiles keep the registers and look up just before loading.
+  constexpr bool LOOK = BM * BN <= 64 * 64;
   const int64_t ktiles = ke > kb ? (ke - kb + BK - 1) / BK : 0;
   if (ktiles > 0) {
-    la.load(A, p.aK, kb, ke, tid);
-    lb.load(B, p.bK, kb, ke, tid);
+    la.koffs(p.aK, kb, ke, tid);
+    lb.koffs(p.bK, kb, ke, tid);
+    la.load(A);
+    lb.load(B);
+    if (LOOK && ktiles > 1) {
+      la.koffs(p.aK, kb + BK, ke, tid);
+      lb.koffs(p.bK, kb + BK, ke, tid);
+    }
     la.store(sA0, tid);
     lb.store(sB0, tid);
   }
@@ -170,8 +190,16 @@ __device__ inline void gett_tile(const GettParams& p, int64_t m0, int64_t n0, in
     const int cur = kt & 1;
     const bool more = kt + 1 < ktiles;
     if (more) {
-      la.load(A, p.aK, kb + (kt + 1) * BK, ke, tid);
-      lb.load(B, p.bK, kb + (kt + 1) * BK, ke, tid);
+      if constexpr (!LOOK) {
+        la.koffs(p.aK, kb + (kt + 1) * BK, ke, tid);
+        lb.koffs(p.bK, kb + (kt + 1) * BK, ke, tid);
+      }
+      la.load(A);
+      lb.load(B);
+      if (LOOK && kt + 2 < ktiles) {
+        la.koffs(p.aK, kb + (kt + 2) * BK, ke, tid);
+        lb.koffs(p.bK, kb + (kt + 2) * BK, ke, tid);
+      }
     }
     Frags<BM, BK, AKF, TM> fa;
     Frags<BN, BK, BKF, TN> fb;
@@ -233,7 +261,7 @@ __device__ inline void gett_tile(const GettParams& p, int64_t m0, int64_t n0, in
 // order (a fixed order, so the result does not depend on which workgroup
 // finished last) and writes alpha * sum + beta * C.
 template <int BM, int BN>
-__device__ inline void gett_reduce_tile(const GettParams& p, int64_t m0, int64_t n0, int64_t l,
+TC_DEV void gett_reduce_tile(const GettParams& p, int64_t m0, int64_t n0, int64_t l,
                                         const double* __restrict__ parts, int S) {
   double* __restrict__ C = p.C + off_at(p.cL, l);
   for (int e = threadIdx.x; e < BM * BN; e += blockDim.x) {

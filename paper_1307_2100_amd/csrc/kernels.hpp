@@ -6,6 +6,10 @@
 
 #include <cstdint>
 
+// Device helpers are always inlined: a real call would cost the calling
+// kernel its register budget (the callee cannot share the caller's).
+#define TC_DEV __device__ __attribute__((always_inline)) inline
+
 namespace tc {
 
 constexpr int kMaxRank = 16;
@@ -27,7 +31,7 @@ inline FastDiv make_fastdiv(uint32_t d) {
   f.shift = (uint32_t)(p - 32);
   return f;
 }
-__device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f) {
+TC_DEV uint32_t fdiv(uint32_t n, const FastDiv& f) {
   return f.d == 1 ? n : (__umulhi(n, f.mul) >> f.shift);
 }
 
@@ -44,7 +48,7 @@ __host__ __device__ inline int64_t off_at(const Offs& o, int64_t i) { return o.t
 // Workgroups are dealt round-robin to the 8 XCDs; consecutive tiles are
 // gathered on one XCD (sharing its L2), and within an XCD tiles are walked in
 // bands of 8 tile rows so that neighbours reuse the same rows and columns.
-__device__ inline void xcd_tile(int64_t bid, int64_t total, int64_t tilesM, int64_t tilesN, int64_t* tm,
+TC_DEV void xcd_tile(int64_t bid, int64_t total, int64_t tilesM, int64_t tilesN, int64_t* tm,
                                 int64_t* tn) {
   const int64_t q = total / 8, r = total % 8;
   const int64_t xcd = bid % 8, loc = bid / 8;
@@ -171,10 +175,13 @@ struct SlabDesc {
   int n;                 // modes of the operand inside one slab
   int size;              // entries per slab
   int batch_fast;        // the batch index varies fastest in memory
+  int dense;             // the slab's modes are dense in their storage order: entry r at r * s0
+  int contig;            // dense, s0 = 1 and consecutive batch indices' slabs follow each other
+  int64_t s0;            // global stride of the slab's storage order (dense only)
   FastDiv size_div;      // division by size
   FastDiv div[kMaxRank];   // extents, sorted by global stride
   int64_t gstr[kMaxRank];  // global strides
-  int lstr[kMaxRank];    // strides in the canonical LDS slab
+  int lstr[kMaxRank];    // strides in the canonical LDS slab (operands that are not dense)
 };
 struct BatchedParams {
   const double* A;
@@ -182,6 +189,9 @@ struct BatchedParams {
   double* C;
   Offs aL, bL, cL;
   SlabDesc a, b, c;
+  // LDS offsets of the group indices inside one point's slab: the storage
+  // order for dense operands, the canonical [m][k] / [n][k] / [m][n] otherwise
+  Offs am, ak, bn, bk, cm, cn;
   int M, N, K;           // per-point group sizes
   int P;                 // batch indices per workgroup
   FastDiv P_div, N_div, sC_div;
@@ -189,6 +199,12 @@ struct BatchedParams {
   double alpha, beta;
 };
 constexpr int kBatchedLdsDoubles = 2048;  // 16 KB of LDS per workgroup: several workgroups per CU
+// Points per workgroup for per-point slabs of `per` doubles and K contracted
+// indices (the contracted offsets of A and B are staged in LDS as well).
+inline int slab_points(int per, int K, int lds_doubles) {
+  const int P = (lds_doubles - K) / per;
+  return P > 64 ? 64 : P;
+}
 hipError_t launch_batched_small(const BatchedParams& bp, hipStream_t s);
 
 // Persistent batches.  Tile configurations of the batch kernel (id, rows,
@@ -204,17 +220,26 @@ constexpr int kNumBatchTiles = 6;
 constexpr int kBatchTileBM[kNumBatchTiles] = {64, 32, 32, 64, 32, 64};
 constexpr int kBatchTileBN[kNumBatchTiles] = {64, 32, 32, 64, 32, 64};
 constexpr int kBatchSlabLdsDoubles = 2048;  // slab LDS of batch tasks (16 KB)
+// Task kinds of the batch kernel.
+enum BatchKind {
+  kBatchGemm = 0,        // one GEMM tile (or one contracted segment of it)
+  kBatchSlab = 1,        // the slabs of P batch indices
+  kBatchLanesK = 2,      // 4 outputs, one wavefront each, lanes along the contracted index
+  kBatchLanesOut = 3     // 256 outputs along lanes, each walking one contracted segment
+};
+constexpr int kLanesKOutputs = 4;      // outputs per lanes-over-k task (one per wavefront)
+constexpr int kLanesOutOutputs = 256;  // outputs per lanes-over-outputs task (one per thread)
 struct BatchItem {       // one contraction of a batch (layout only)
-  GettParams g;          // kind 0: GEMM tiles
+  GettParams g;          // kinds 0, 2, 3
   BatchedParams b;       // kind 1: slabs of batch indices
   int kind;
   int akf, bkf, swapped;
   int64_t tilesM, tilesN;
-  int ksplit;            // kind 0: contracted segments per tile (1 = none)
-  int pad;
+  int ksplit;            // contracted segments per task group (1 = none)
+  int n_fastest;         // kind 3: consecutive lanes along n (else along m)
   int64_t seg_len;       // contracted indices per segment
-  int64_t part_off;      // first partial tile of this item (in tiles of BM*BN doubles)
-  int64_t cnt_off;       // first tile counter of this item
+  int64_t part_off;      // first partial sum of this item (in doubles)
+  int64_t cnt_off;       // first completion counter of this item
 };
 struct BatchPtrs {       // per execution
   const double* A;
@@ -224,8 +249,8 @@ struct BatchPtrs {       // per execution
 };
 struct BatchTask {
   int item;
-  int seg;               // contracted segment (kind 0 with ksplit > 1)
-  int64_t idx;           // tile index (kind 0) or slab index (kind 1)
+  int seg;               // contracted segment (ksplit > 1)
+  int64_t idx;           // tile (kind 0), slab (1) or output group (2, 3) index
 };
 struct BatchLaunch {
   const BatchItem* items;
@@ -235,8 +260,8 @@ struct BatchLaunch {
   const int64_t* chunks;       // chunk c holds tasks [chunks[c], chunks[c+1])
   int64_t nchunks;
   unsigned long long* counter;
-  double* parts;               // partial tiles of split items
-  unsigned* tile_cnt;          // segments finished per split tile
+  double* parts;               // partial sums of split items
+  unsigned* tile_cnt;          // segments finished per split tile or output group
   int64_t n_cnt;
   int config;
   int slab_lds_doubles;

@@ -148,7 +148,7 @@ bool batched_fits(const tc_plan_info& info, const Group* G) {
   if (G[GL].n == 0 || info.L < 64) return false;
   if (info.M > 1024 || info.N > 1024 || info.K > 1024) return false;
   const int64_t per = info.M * info.K + info.N * info.K + info.M * info.N;
-  return per * 2 <= kBatchedLdsDoubles;
+  return per * 2 + info.K <= kBatchedLdsDoubles;
 }
 
 // Slab descriptors: each operand's non-batch modes sorted by global stride,
@@ -184,11 +184,18 @@ void build_slabs(Analysis& an) {
     an.slab_size[slot] = size;
     const int64_t min_slab = modes.empty() ? INT64_MAX : std::get<0>(modes[0]);
     an.slab_batch_fast[slot] = G[GL].n > 0 && G[GL].str[slot][0] < min_slab ? 1 : 0;
+    // dense: each mode's stride is the previous one times its extent, so the
+    // slab is one strided run in storage order
+    bool dense = !modes.empty() && std::get<0>(modes[0]) > 0;
+    for (size_t i = 1; dense && i < modes.size(); ++i)
+      dense = std::get<0>(modes[i]) == std::get<0>(modes[i - 1]) * std::get<1>(modes[i - 1]);
+    an.slab_dense[slot] = dense ? 1 : 0;
+    an.slab_s0[slot] = dense ? std::get<0>(modes[0]) : 0;
   }
   const int per = an.slab_size[0] + an.slab_size[1] + an.slab_size[2];
-  int P = kBatchedLdsDoubles / per;
-  an.batched_P = P > 64 ? 64 : P;
+  an.batched_P = slab_points(per, (int)K, kBatchedLdsDoubles);
   (void)M;
+  (void)N;
 }
 
 }  // namespace

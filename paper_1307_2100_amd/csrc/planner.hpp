@@ -73,7 +73,8 @@ struct Analysis {
   int64_t elems[3] = {};    // entries of kernel A, kernel B, C (products of extents)
   // batched small contractions: slab descriptors (without pointers)
   int batched_P = 0;
-  int slab_n[3] = {}, slab_size[3] = {}, slab_batch_fast[3] = {};
+  int slab_n[3] = {}, slab_size[3] = {}, slab_batch_fast[3] = {}, slab_dense[3] = {};
+  int64_t slab_s0[3] = {};
   int slab_ext[3][TC_MAX_RANK] = {};
   int64_t slab_gstr[3][TC_MAX_RANK] = {};
   int slab_lstr[3][TC_MAX_RANK] = {};

@@ -21,7 +21,12 @@ def _make_batch(count, seed, kind="integers"):
     g = np.random.default_rng(seed)
     specs = [synth.workload_gr_r((6, 5, 4)), synth.workload_gr_s((6, 5, 4)),
              ("akb", "kbc", "ac", {"a": 31, "k": 300, "b": 37, "c": 5}),      # split-K tasks
-             ("ikm", "kj", "ijm", {"i": 70, "k": 3000, "m": 2, "j": 9})]
+             ("ikm", "kj", "ijm", {"i": 70, "k": 3000, "m": 2, "j": 9}),
+             # memory-bound shapes kept on their lanes kernels, long contracted ranges in segments
+             ("ki", "k", "i", {"k": 40000, "i": 7}),                             # lanes over k, 3 segments
+             ("kb", "kb", "b", {"k": 50000, "b": 3}),                            # inner products per b
+             ("ik", "k", "i", {"i": 300, "k": 3000}),                            # lanes over outputs, segments
+             ("ik", "kj", "ij", {"i": 600, "k": 300, "j": 1})]
     for _ in range(count):
         specs.append(synth.random_contraction(g, rank_range=(3, 6), ext_range=(2, 9), max_elems=20000,
                                               p_outer=0.03, allow_batch=True))
@@ -45,6 +50,21 @@ def _check_exact(entries, alphas=None):
         if alphas is not None:
             ref = alphas[i] * ref
         assert np.array_equal(e["C"].cpu().numpy(), ref), (i, e["spec"])
+
+
+def test_memory_bound_shapes_keep_their_lanes_kernels():
+    for la, lb, lc, ext, kernel in (("ki", "k", "i", {"k": 40000, "i": 7}, "lanes_over_k"),
+                                    ("kb", "kb", "b", {"k": 50000, "b": 3}, "lanes_over_k"),
+                                    ("ik", "k", "i", {"i": 300, "k": 3000}, "lanes_over_outputs")):
+        shapes = [[ext[l] for l in x] for x in (la, lb, lc)]
+        descs = []
+        for x, lab in zip(shapes, (la, lb, lc)):
+            st, acc = [], 1
+            for e in x:
+                st.append(acc)
+                acc *= e
+            descs.append(tc.Desc(x, st, lab))
+        assert tc.KERNEL_NAMES[tc.tc_analyze(*descs).kernel] == kernel, (la, lb, lc)
 
 
 def test_batch_matches_oracle_graph_and_eager():
