@@ -8,7 +8,14 @@ each through tc_execute on plans built once.  Inputs are seeded synthetic
 FP64 tensors (uniform in [-1, 1], column-major) resident in HBM before the
 timed region.  Prints one JSON line.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--split]
+Besides the step, the JSON line carries (outside the timed region) the
+split-precision runs on the same inputs, the batch workload (general-
+relativity grid contractions plus 2000 random contractions in one persistent
+graph-replayed launch), the memory-bound kernels' HBM rates, and the oracle
+timed on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-split] [--no-batch]
+                       [--precision-workload]
 """
 import argparse
 import hashlib
@@ -35,6 +42,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU sample")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision runs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch workload and memory-bound kernels")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--precision-workload", action="store_true",
                     help="also run the precision workload (v=192, o=48, N(0,1)*10^U(-3,3) inputs)")
     return ap.parse_args()
@@ -72,6 +82,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read, 1 GiB written
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: %d bytes read, %d bytes written" % (x.numel() * 8, y.numel() * 8),
+              file=sys.stderr, flush=True)
+        del x, y
+        torch.cuda.empty_cache()
 
     work = {}
     for name, spec, wid in (("cc_a", synth.workload_cc_a(args.v, args.o), 1),
@@ -165,6 +186,11 @@ def main():
     if not args.no_split:
         split = split_runs(work, max(3, min(args.steps, 10)))
 
+    batch = memory = None
+    if not args.no_batch:
+        batch = batch_runs()
+        memory = memory_bound_runs()
+
     precision_workload = None
     if args.precision_workload:
         for w in work.values():
@@ -195,6 +221,8 @@ def main():
         "per_contraction": per_contraction,
         "split_precision": split,
         "precision_workload": precision_workload,
+        "batch_workload": batch,
+        "memory_bound_kernels": memory,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -291,6 +319,133 @@ def precision_runs(args):
         print("[bench] precision workload %s: %s" % (name, res), file=sys.stderr, flush=True)
         del dA, dB, C
         torch.cuda.empty_cache()
+    return out
+
+
+def _dev_uniform(tc, torch, shape, gen):
+    t = tc.empty_colmajor(list(shape), device="cuda")
+    t.uniform_(-1.0, 1.0, generator=gen)
+    return t
+
+
+def _events_ms(fn, reps):
+    """Mean time of fn() over reps back-to-back calls, HIP events on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batch_runs(n_random=2000, reps=10):
+    """The batch workload: R[a,b] = T[a,c,b,d] g[c,d] and S[a,b,c] = G[a,b,d] V[d,c]
+    on a 128^3 grid (every extent 4) plus n_random contractions of rank 3-6,
+    extents uniform in [4, 64], random storage orders and contracted sets, in
+    one persistent launch replayed from a graph with the autotuned tile
+    configuration.  Roofline: the sum over contractions of max(flops / FP64
+    peak, bytes / HBM peak) against the measured time."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1307_2100_amd as tc
+    import synth
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1307)
+    g = np.random.default_rng(1307)
+    specs = [synth.workload_gr_r(), synth.workload_gr_s()]
+    specs += [synth.random_contraction(g, rank_range=(3, 6), ext_range=(4, 64), max_elems=1 << 20)
+              for _ in range(n_random)]
+    ents = []
+    for la, lb, lc, ext in specs:
+        A = _dev_uniform(tc, torch, synth.shape_of(la, ext), gen)
+        B = _dev_uniform(tc, torch, synth.shape_of(lb, ext), gen)
+        C = tc.empty_colmajor(list(synth.shape_of(lc, ext)))
+        C.zero_()
+        ents.append((la, lb, lc, ext, A, B, C, tc.Plan.for_tensors(A, la, B, lb, C, lc)))
+    flops = sum(e[7].info.flops for e in ents)
+    nbytes = sum(e[7].info.bytes for e in ents)
+    ideal_ms = sum(max(e[7].info.flops / FP64_PEAK_TFLOPS / 1e9, e[7].info.bytes / HBM_PEAK_GBS / 1e6)
+                   for e in ents)
+    # each grid contraction alone (slab kernel)
+    gr = {}
+    for name, e in zip(("gr_r", "gr_s"), ents[:2]):
+        ms = _events_ms(lambda: e[7].execute(e[4], e[5], e[6]), reps)
+        gr[name] = {"ms": round(ms, 4), "gb_s": round(e[7].info.bytes / ms / 1e6, 1),
+                    "frac_hbm_peak": round(e[7].info.bytes / ms / 1e6 / HBM_PEAK_GBS, 4),
+                    "kernel": tc.KERNEL_NAMES[e[7].info.kernel]}
+    batch = tc.Batch([e[7] for e in ents])
+    As, Bs, Cs = [e[4] for e in ents], [e[5] for e in ents], [e[6] for e in ents]
+    t0 = time.perf_counter()
+    best, _ = batch.autotune(As, Bs, Cs)
+    tune_s = time.perf_counter() - t0
+    batch.set_options(best, 1)
+    batch.bind(As, Bs, Cs)
+    ms = _events_ms(batch.run, reps)
+    q = batch.query()
+    # sampled check of a few entries of the grid contractions and of some random ones
+    err = 0.0
+    checked = [e for e in ents if e[2]][:12]
+    for e in checked:
+        la, lb, lc, ext, A, B, C = e[:7]
+        shape = [ext[l] for l in lc]
+        gi = np.random.default_rng(5)
+        idx = np.stack([gi.integers(0, x, 64) for x in shape], axis=1)
+        s, a = oracle.contract_entries(A.cpu().numpy(), la, B.cpu().numpy(), lb, lc, idx)
+        got = C.cpu().numpy()[tuple(idx.T)]
+        err = max(err, float(np.max(np.abs(got - s) / np.where(a > 0, a, 1.0))))
+    batch.close()
+    for e in ents:
+        e[7].close()
+    del ents, As, Bs, Cs
+    torch.cuda.empty_cache()
+    return {"contractions": len(specs), "tasks": q["ntasks"], "tile_config": best, "autotune_s": round(tune_s, 2),
+            "ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 1), "gb_s": round(nbytes / ms / 1e6, 1),
+            "ideal_ms": round(ideal_ms, 4), "frac_roofline": round(ideal_ms / ms, 4),
+            "max_componentwise_error_sampled": err, "grid_contractions_alone": gr}
+
+
+def memory_bound_runs(reps=20):
+    """HBM rates of the memory-bound kernels on large operands: the LDS-tiled
+    permute (COPY step), GEMV with lanes along the outputs and along k, DOT
+    with segmented sums.  Bytes are the algorithmic ones (each operand read
+    once, the output written once)."""
+    import torch
+
+    import paper_1307_2100_amd as tc
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    out = {}
+    # permute: 256^3 x 8 tensor (1 GiB), its first two modes exchanged in storage
+    X = _dev_uniform(tc, torch, (256, 256, 256, 8), gen)
+    Y = torch.empty(X.numel(), dtype=torch.float64, device="cuda")
+    strides = [256, 1, 256 * 256, 256 ** 3]
+    ms = _events_ms(lambda: tc.permute(X, strides, Y), reps)
+    out["permute"] = {"ms": round(ms, 4), "gb_s": round(16.0 * X.numel() / ms / 1e6, 1)}
+    del X, Y
+    cases = {
+        "gemv_lanes_over_outputs": ("ik", "k", "i", {"i": 32768, "k": 8192}),
+        "gemv_lanes_over_k": ("ki", "k", "i", {"k": 32768, "i": 8192}),
+        "dot": ("k", "k", "", {"k": 1 << 27}),
+    }
+    for name, (la, lb, lc, ext) in cases.items():
+        A = _dev_uniform(tc, torch, [ext[l] for l in la], gen)
+        B = _dev_uniform(tc, torch, [ext[l] for l in lb], gen)
+        C = tc.empty_colmajor([ext[l] for l in lc])
+        plan = tc.Plan.for_tensors(A, la, B, lb, C, lc)
+        ws = plan.workspace(C.device)
+        ms = _events_ms(lambda: plan.execute(A, B, C, workspace=ws), reps)
+        out[name] = {"ms": round(ms, 4), "gb_s": round(plan.info.bytes / ms / 1e6, 1),
+                     "frac_hbm_peak": round(plan.info.bytes / ms / 1e6 / HBM_PEAK_GBS, 4),
+                     "kernel": tc.KERNEL_NAMES[plan.info.kernel]}
+        plan.close()
+        del A, B, C
+    torch.cuda.empty_cache()
     return out
 
 

@@ -18,6 +18,7 @@
 // so one captured graph serves every execution of the batch.
 #include "batched_slab.hpp"
 #include "gett_tile.hpp"
+#include "lanes.hpp"
 
 namespace tc {
 namespace {
@@ -73,16 +74,7 @@ TC_DEV void batch_lanes_k(const BatchItem& it, const GettParams& p, const BatchT
     const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
     const int64_t k0 = (int64_t)task.seg * it.seg_len;
     const int64_t k1 = k0 + it.seg_len < p.K ? k0 + it.seg_len : p.K;
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    int64_t k = k0 + lane;
-    for (; k + 192 < k1; k += 256) {
-      acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
-      acc1 += A[off_at(p.aK, k + 64)] * B[off_at(p.bK, k + 64)];
-      acc2 += A[off_at(p.aK, k + 128)] * B[off_at(p.bK, k + 128)];
-      acc3 += A[off_at(p.aK, k + 192)] * B[off_at(p.bK, k + 192)];
-    }
-    for (; k < k1; k += 64) acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
-    v = batch_wave_sum((acc0 + acc1) + (acc2 + acc3));
+    v = batch_wave_sum(lanes_k_dot(A, B, p.aK, p.bK, k0, k1, lane));
   }
   if (S == 1) {
     if (o < outputs && lane == 0) batch_store(p, m, n, l, v);
@@ -124,16 +116,7 @@ TC_DEV void batch_lanes_out(const BatchItem& it, const GettParams& p, const Batc
     const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
     const int64_t k0 = (int64_t)task.seg * it.seg_len;
     const int64_t k1 = k0 + it.seg_len < p.K ? k0 + it.seg_len : p.K;
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    int64_t k = k0;
-    for (; k + 4 <= k1; k += 4) {
-      acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
-      acc1 += A[off_at(p.aK, k + 1)] * B[off_at(p.bK, k + 1)];
-      acc2 += A[off_at(p.aK, k + 2)] * B[off_at(p.bK, k + 2)];
-      acc3 += A[off_at(p.aK, k + 3)] * B[off_at(p.bK, k + 3)];
-    }
-    for (; k < k1; ++k) acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
-    v = (acc0 + acc1) + (acc2 + acc3);
+    v = lanes_out_dot(A, B, p.aK, p.bK, k0, k1);
   }
   if (S == 1) {
     if (o < outputs) batch_store(p, m, n, l, v);

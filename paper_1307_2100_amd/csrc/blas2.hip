@@ -14,7 +14,7 @@
 //    outputs exist, the contracted range is cut into segments whose partial
 //    sums go to the workspace and a second pass adds them in a fixed order
 //    (deterministic).
-#include "kernels.hpp"
+#include "lanes.hpp"
 
 namespace tc {
 namespace {
@@ -36,16 +36,7 @@ __global__ __launch_bounds__(256) void lanes_over_outputs_kernel(GettParams p, i
   }
   const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
   const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  int64_t k = 0;
-  for (; k + 4 <= p.K; k += 4) {
-    acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
-    acc1 += A[off_at(p.aK, k + 1)] * B[off_at(p.bK, k + 1)];
-    acc2 += A[off_at(p.aK, k + 2)] * B[off_at(p.bK, k + 2)];
-    acc3 += A[off_at(p.aK, k + 3)] * B[off_at(p.bK, k + 3)];
-  }
-  for (; k < p.K; ++k) acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
-  const double s = (acc0 + acc1) + (acc2 + acc3);
+  const double s = lanes_out_dot(A, B, p.aK, p.bK, 0, p.K);
   double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
   *dst = p.beta == 0.0 ? p.alpha * s : p.alpha * s + p.beta * *dst;
 }
@@ -72,14 +63,7 @@ __global__ __launch_bounds__(256) void lanes_over_k_kernel(GettParams p, int64_t
   const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
   const int64_t k0 = s * seg_len;
   const int64_t k1 = k0 + seg_len < p.K ? k0 + seg_len : p.K;
-  double acc0 = 0.0, acc1 = 0.0;
-  int64_t k = k0 + lane;
-  for (; k + 64 < k1; k += 128) {
-    acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
-    acc1 += A[off_at(p.aK, k + 64)] * B[off_at(p.bK, k + 64)];
-  }
-  if (k < k1) acc0 += A[off_at(p.aK, k)] * B[off_at(p.bK, k)];
-  const double v = wave_sum(acc0 + acc1);
+  const double v = wave_sum(lanes_k_dot(A, B, p.aK, p.bK, k0, k1, lane));
   if (lane != 0) return;
   if (seg == 1) {
     double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);

@@ -1,0 +1,77 @@
+// Inner loops of the memory-bound recipes (GEMV, DOT, fused GER sums),
+// shared by their own kernels and by the persistent batch kernel.
+//
+// A contracted group of several modes is addressed through offset tables, so
+// each element costs a table lookup before its load.  Both loops look up the
+// offsets of their next step while the loads of the current step are in
+// flight, so a step waits on one memory latency, not two in a row.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace tc {
+
+// Lanes along k: this lane's share of sum_k A[aK(k)] B[bK(k)] over
+// k = k0 + lane, k0 + lane + 64, ... below k1 (four independent sums).
+TC_DEV double lanes_k_dot(const double* __restrict__ A, const double* __restrict__ B, const Offs& aK,
+                          const Offs& bK, int64_t k0, int64_t k1, int lane) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t oa[4], ob[4];
+  int64_t k = k0 + lane;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t kk = k + 64 * u;
+    oa[u] = kk < k1 ? off_at(aK, kk) : -1;
+    ob[u] = kk < k1 ? off_at(bK, kk) : -1;
+  }
+  for (; k < k1; k += 256) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = oa[u] >= 0 ? A[oa[u]] : 0.0;
+      b[u] = ob[u] >= 0 ? B[ob[u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t kk = k + 256 + 64 * u;
+      oa[u] = kk < k1 ? off_at(aK, kk) : -1;
+      ob[u] = kk < k1 ? off_at(bK, kk) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += a[u] * b[u];
+  }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// One output per thread: sum_k A[aK(k)] B[bK(k)] over k in [k0, k1) in order
+// of four interleaved sums (all lanes of a wavefront walk the same k).
+TC_DEV double lanes_out_dot(const double* __restrict__ A, const double* __restrict__ B, const Offs& aK,
+                            const Offs& bK, int64_t k0, int64_t k1) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t oa[4], ob[4];
+  int64_t k = k0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    oa[u] = k + u < k1 ? off_at(aK, k + u) : -1;
+    ob[u] = k + u < k1 ? off_at(bK, k + u) : -1;
+  }
+  for (; k < k1; k += 4) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = oa[u] >= 0 ? A[oa[u]] : 0.0;
+      b[u] = ob[u] >= 0 ? B[ob[u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t kk = k + 4 + u;
+      oa[u] = kk < k1 ? off_at(aK, kk) : -1;
+      ob[u] = kk < k1 ? off_at(bK, kk) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += a[u] * b[u];
+  }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+}  // namespace tc

@@ -147,9 +147,12 @@ def collect(out, n, seed=0, log_every=200):
 
 
 def load_records(paths):
+    """Records of one or more collection files (plain or gzip-compressed JSON lines)."""
+    import gzip
     recs = []
     for p in paths:
-        with open(p) as f:
+        opener = gzip.open if p.endswith(".gz") else open
+        with opener(p, "rt") as f:
             recs.extend(json.loads(line) for line in f if line.strip())
     return recs
 
@@ -184,7 +187,7 @@ def normalisation(X):
     return mean.astype(np.float32), std.astype(np.float32)
 
 
-def train(X, T, M, epochs=60, batch=256, lr=2e-3, seed=0, log=print):
+def train(X, T, M, epochs=100, batch=256, lr=3e-3, seed=0, log=print):
     """Trains the picker network on the GPU with the libtc kernels (Adam,
     masked MSE, learning rate decayed linearly to lr/20); returns (params,
     mean, std, history of mean training loss per epoch)."""
@@ -331,7 +334,7 @@ def main(argv=None):
     t = sub.add_parser("train")
     t.add_argument("--data", nargs="+", required=True)
     t.add_argument("--test", type=int, default=5000)
-    t.add_argument("--epochs", type=int, default=60)
+    t.add_argument("--epochs", type=int, default=100)
     t.add_argument("--out", default=DEFAULT_MODEL)
     t.add_argument("--report", default=None)
     e = sub.add_parser("evaluate")
