@@ -50,19 +50,25 @@ def parse():
     return ap.parse_args()
 
 
-def sha_of(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+GETT_SOURCES = [os.path.join(ROOT, "paper_1307_2100_amd", "csrc", f) for f in ("gett_f64.hip", "gett_tile.hpp")]
 
 
-def traffic_from_profile(kernel_src):
+def sha_of(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_srcs):
     """HBM traffic of the dominant kernel from committed counter runs, valid
     only while the kernel source is unchanged since they were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_gett_f64_cc_a.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_source_sha") != sha_of(kernel_src):
+    if rec.get("kernel_source_sha") != sha_of(kernel_srcs):
         return None
     return rec.get("bytes_per_launch")
 
@@ -172,9 +178,8 @@ def main():
     ia = work["cc_a"]["plan"].info
     ms_a = float(np.mean(per["cc_a"]))
     achieved = ia.flops / (ms_a * 1e-3) / 1e12
-    kernel_src = os.path.join(ROOT, "paper_1307_2100_amd", "csrc", "gett_f64.hip")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic_from_profile(kernel_src),
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic_from_profile(GETT_SOURCES),
                 "kernel": "gett_f64_kernel (contraction a)", "algorithmic_flops_per_launch": ia.flops,
                 "algorithmic_bytes_per_launch": ia.bytes}
 
@@ -379,6 +384,7 @@ def batch_runs(n_random=2000, reps=10):
         gr[name] = {"ms": round(ms, 4), "gb_s": round(e[7].info.bytes / ms / 1e6, 1),
                     "frac_hbm_peak": round(e[7].info.bytes / ms / 1e6 / HBM_PEAK_GBS, 4),
                     "kernel": tc.KERNEL_NAMES[e[7].info.kernel]}
+    print("[bench] batch workload: %d plans built" % len(ents), file=sys.stderr, flush=True)
     batch = tc.Batch([e[7] for e in ents])
     As, Bs, Cs = [e[4] for e in ents], [e[5] for e in ents], [e[6] for e in ents]
     t0 = time.perf_counter()
@@ -388,6 +394,7 @@ def batch_runs(n_random=2000, reps=10):
     batch.bind(As, Bs, Cs)
     ms = _events_ms(batch.run, reps)
     q = batch.query()
+    print("[bench] batch workload: config %d, %.3f ms per execution" % (best, ms), file=sys.stderr, flush=True)
     # sampled check of a few entries of the grid contractions and of some random ones
     err = 0.0
     checked = [e for e in ents if e[2]][:12]
@@ -426,7 +433,9 @@ def memory_bound_runs(reps=20):
     Y = torch.empty(X.numel(), dtype=torch.float64, device="cuda")
     strides = [256, 1, 256 * 256, 256 ** 3]
     ms = _events_ms(lambda: tc.permute(X, strides, Y), reps)
-    out["permute"] = {"ms": round(ms, 4), "gb_s": round(16.0 * X.numel() / ms / 1e6, 1)}
+    out["permute"] = {"ms": round(ms, 4), "gb_s": round(16.0 * X.numel() / ms / 1e6, 1),
+                      "frac_hbm_peak": round(16.0 * X.numel() / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    print("[bench] permute: %s" % out["permute"], file=sys.stderr, flush=True)
     del X, Y
     cases = {
         "gemv_lanes_over_outputs": ("ik", "k", "i", {"i": 32768, "k": 8192}),

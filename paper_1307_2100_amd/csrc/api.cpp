@@ -764,7 +764,8 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
     return e == hipSuccess ? TC_OK : hip_fail(e, "batched launch");
   }
   if (an.kernel == tc::Analysis::KERNEL_LANES_OUT) {
-    e = tc::launch_lanes_over_outputs(gp, an.n_fastest, s);
+    double* part = an.seg > 1 ? (double*)((char*)workspace + an.part_offset) : nullptr;
+    e = tc::launch_lanes_over_outputs(gp, an.n_fastest, an.seg, part, s);
     return e == hipSuccess ? TC_OK : hip_fail(e, "lanes-over-outputs launch");
   }
   if (an.kernel == tc::Analysis::KERNEL_LANES_K) {

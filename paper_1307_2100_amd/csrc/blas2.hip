@@ -19,7 +19,12 @@
 namespace tc {
 namespace {
 
-__global__ __launch_bounds__(256) void lanes_over_outputs_kernel(GettParams p, int n_fastest, int64_t total) {
+// One thread per (output entry, contracted segment); blockIdx.y is the
+// segment.  seg == 1 writes C; otherwise the partial sum goes to
+// part[s * total + o] (consecutive outputs adjacent).
+__global__ __launch_bounds__(256) void lanes_over_outputs_kernel(GettParams p, int n_fastest, int64_t total,
+                                                                 int64_t seg, int64_t seg_len,
+                                                                 double* __restrict__ part) {
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= total) return;
   int64_t m, n, l;
@@ -36,9 +41,39 @@ __global__ __launch_bounds__(256) void lanes_over_outputs_kernel(GettParams p, i
   }
   const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
   const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
-  const double s = lanes_out_dot(A, B, p.aK, p.bK, 0, p.K);
+  const int64_t s = blockIdx.y;
+  const int64_t k0 = s * seg_len;
+  const int64_t k1 = k0 + seg_len < p.K ? k0 + seg_len : p.K;
+  const double v = lanes_out_dot(A, B, p.aK, p.bK, k0, k1);
+  if (seg > 1) {
+    part[s * total + o] = v;
+    return;
+  }
   double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
-  *dst = p.beta == 0.0 ? p.alpha * s : p.alpha * s + p.beta * *dst;
+  *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
+}
+
+// Second pass of the segmented form: output o adds its partial sums in segment order.
+__global__ __launch_bounds__(256) void sum_out_partials_kernel(GettParams p, int n_fastest, int64_t total,
+                                                               int64_t seg, const double* __restrict__ part) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= total) return;
+  double v = 0.0;
+  for (int64_t s = 0; s < seg; ++s) v += part[s * total + o];
+  int64_t m, n, l;
+  if (n_fastest) {
+    n = o % p.N;
+    const int64_t r = o / p.N;
+    m = r % p.M;
+    l = r / p.M;
+  } else {
+    m = o % p.M;
+    const int64_t r = o / p.M;
+    n = r % p.N;
+    l = r / p.N;
+  }
+  double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
+  *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -94,14 +129,30 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(GettParams p, int64_t
 
 }  // namespace
 
-hipError_t launch_lanes_over_outputs(const GettParams& p, bool n_fastest, hipStream_t s) {
+hipError_t launch_lanes_over_outputs(const GettParams& p, bool n_fastest, int64_t seg, double* part, hipStream_t s) {
   const int64_t total = p.M * p.N * p.L;
   if (total == 0) return hipSuccess;
+  if (seg < 1 || !part) seg = 1;
   const int64_t blocks = (total + 255) / 256;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(lanes_over_outputs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n_fastest ? 1 : 0,
-                     total);
+  if (blocks > 0x7fffffffLL || seg > 65535) return hipErrorInvalidConfiguration;
+  const int64_t seg_len = (p.K + seg - 1) / seg;
+  hipLaunchKernelGGL(lanes_over_outputs_kernel, dim3((unsigned)blocks, (unsigned)seg), dim3(256), 0, s, p,
+                     n_fastest ? 1 : 0, total, seg, seg_len, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || seg == 1) return e;
+  hipLaunchKernelGGL(sum_out_partials_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n_fastest ? 1 : 0, total,
+                     seg, part);
   return hipGetLastError();
+}
+
+int64_t out_segments(int64_t outputs, int64_t K) {
+  const int64_t blocks = (outputs + 255) / 256;
+  const int64_t target_blocks = 256 * 4;
+  if (blocks >= target_blocks || K < 512) return 1;
+  int64_t seg = (target_blocks + blocks - 1) / blocks;
+  const int64_t max_seg = K / 256;
+  if (seg > max_seg) seg = max_seg;
+  return seg < 1 ? 1 : seg;
 }
 
 hipError_t launch_lanes_over_k(const GettParams& p, int64_t seg, double* part, hipStream_t s) {

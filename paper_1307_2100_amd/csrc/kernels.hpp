@@ -124,7 +124,12 @@ inline void choose_split(int64_t tiles, int64_t K, int bk, int* split, int64_t* 
 
 // GEMV / GER family: one thread per output entry walking the contracted
 // index (consecutive lanes along n when n_fastest, else along m).
-hipError_t launch_lanes_over_outputs(const GettParams& p, bool n_fastest, hipStream_t s);
+// seg > 1: the contracted range is cut into seg segments whose partial sums
+// go to part (outputs * seg doubles) and are added in segment order.
+hipError_t launch_lanes_over_outputs(const GettParams& p, bool n_fastest, int64_t seg, double* part, hipStream_t s);
+// Contracted segments for lanes-over-outputs: enough workgroups to cover the
+// chip when outputs are few, segments of at least 256 indices.
+int64_t out_segments(int64_t outputs, int64_t K);
 // GEMV-T / DOT family: one wavefront per (output entry, contracted segment);
 // seg > 1 needs part[] of M*N*L*seg doubles and adds a second pass.
 hipError_t launch_lanes_over_k(const GettParams& p, int64_t seg, double* part, hipStream_t s);

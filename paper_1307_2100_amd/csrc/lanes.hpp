@@ -16,6 +16,32 @@ namespace tc {
 TC_DEV double lanes_k_dot(const double* __restrict__ A, const double* __restrict__ B, const Offs& aK,
                           const Offs& bK, int64_t k0, int64_t k1, int lane) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const bool unit = !aK.tab && !bK.tab && aK.stride == 1 && bK.stride == 1;
+  if (unit && ((reinterpret_cast<uintptr_t>(A + k0) | reinterpret_cast<uintptr_t>(B + k0)) & 15) == 0) {
+    // both operands contiguous along k: 16-byte loads, lane l takes pairs
+    // k0 + 2l + 128j (four pairs in flight per step)
+    const d2* __restrict__ A2 = reinterpret_cast<const d2*>(A + k0);
+    const d2* __restrict__ B2 = reinterpret_cast<const d2*>(B + k0);
+    const int64_t pairs = (k1 - k0) >> 1;
+    int64_t q = lane;
+    for (; q + 192 < pairs; q += 256) {
+      d2 a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = A2[q + 64 * u];
+        b[u] = B2[q + 64 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += a[u].x * b[u].x + a[u].y * b[u].y;
+    }
+    for (; q < pairs; q += 64) {
+      const d2 a = A2[q], b = B2[q];
+      acc[0] += a.x * b.x + a.y * b.y;
+    }
+    if (((k1 - k0) & 1) && lane == 0) acc[1] += A[k1 - 1] * B[k1 - 1];
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  }
   int64_t oa[4], ob[4];
   int64_t k = k0 + lane;
 #pragma unroll

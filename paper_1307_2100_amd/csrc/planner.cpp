@@ -567,8 +567,8 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
       lanes_k = matrix_kfast || (outputs < 4096 && info.K > 4096);
     }
     an.kernel = lanes_k ? Analysis::KERNEL_LANES_K : Analysis::KERNEL_LANES_OUT;
-    if (lanes_k && !an.empty_out && !an.empty_sum) {
-      an.seg = k_segments(outputs, info.K);
+    if (!an.empty_out && !an.empty_sum) {
+      an.seg = lanes_k ? k_segments(outputs, info.K) : out_segments(outputs, info.K);
       if (an.seg > 1) {
         an.part_offset = (info.workspace_bytes + 255) / 256 * 256;
         info.workspace_bytes = an.part_offset + (size_t)(outputs * an.seg) * sizeof(double);

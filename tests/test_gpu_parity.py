@@ -167,6 +167,8 @@ def test_permute_entry_point_bit_exact():
     ("gemv_n", "abg", "bg", "a", {"a": 5000, "b": 33, "g": 7}),
     ("gemv_t", "bga", "bg", "a", {"a": 300, "b": 129, "g": 40}),
     ("gemv_few_outputs", "abg", "bg", "a", {"a": 3, "b": 2000, "g": 9}),
+    # lanes over outputs with few outputs and a long sum: contracted segments, ordered second pass
+    ("gemv_n_segments", "abg", "bg", "a", {"a": 700, "b": 60, "g": 50}),
 ])
 def test_memory_bound_recipes(case):
     name, labA, labB, labC, ext = case
@@ -178,6 +180,14 @@ def test_memory_bound_recipes(case):
     got, info = _run(labA, labB, labC, A, B, "auto", alpha=0.5)
     ref, absr = reference(A, labA, B, labB, labC, alpha=0.5)
     assert componentwise_error(got, ref, absr) <= FP64_TOL
+
+
+def test_lanes_over_outputs_segments_are_used():
+    labA, labB, labC, ext = "abg", "bg", "a", {"a": 700, "b": 60, "g": 50}
+    A, B = synth.make_operands(15, labA, labB, ext, kind="integers")
+    got, info = _run(labA, labB, labC, A, B, "auto", alpha=2.0, beta=-1.0, C0=synth.integers([700], 3))
+    assert info["kernel_name"] == "lanes_over_outputs" and info["workspace_bytes"] > 0, info
+    assert np.array_equal(got, 2.0 * oracle.contract(A, labA, B, labB, labC) - synth.integers([700], 3))
 
 
 def test_split_k_is_used_and_exact():
