@@ -311,6 +311,8 @@ struct tc_batch_s {
   int n = 0;
   int device = 0;
   int num_cus = 256;
+  int lds_per_cu = 160 * 1024;
+  int slab_lds = tc::kBatchSlabLdsDoubles;  // slab LDS (doubles) of the current configuration
   int config = -1;
   int use_graph = 1;
   int64_t ntasks = 0;
@@ -387,6 +389,18 @@ struct tc_batch_s {
     std::vector<HT> tasks;
     n_cnt = 0;
     n_parts = 0;
+    // Slab tasks take the LDS the configuration's occupancy leaves per
+    // workgroup (more points per task, fewer tasks), within 16 to 64 KB.
+    const int wgs = tc::batch_blocks_per_cu(cfg);
+    // (1 KB per workgroup left for static LDS and allocation granularity)
+    slab_lds = wgs > 0 ? lds_per_cu / (int)sizeof(double) / wgs - 128 : tc::kBatchSlabLdsDoubles;
+    slab_lds = std::min(std::max(slab_lds, tc::kBatchSlabLdsDoubles), tc::kBatchSlabLdsMaxDoubles);
+    for (tc::BatchItem& it : items) {
+      if (it.kind != tc::kBatchSlab) continue;
+      const int per = it.b.a.size + it.b.b.size + it.b.c.size;
+      it.b.P = std::max(1, tc::slab_points(per, it.b.K, slab_lds));
+      it.b.P_div = tc::make_fastdiv((uint32_t)it.b.P);
+    }
     for (int i = 0; i < n; ++i) {
       tc::BatchItem& it = items[i];
       if (it.kind == tc::kBatchLanesK || it.kind == tc::kBatchLanesOut) {
@@ -492,7 +506,7 @@ struct tc_batch_s {
     hipError_t e = hipMemcpyAsync(d_ptrs, h_ptrs, sizeof(tc::BatchPtrs) * n, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
     tc::BatchLaunch bl{d_items, d_ptrs, d_tasks, ntasks, d_chunks, nchunks, counter, parts, cnt, n_cnt, config,
-                       tc::kBatchSlabLdsDoubles, num_cus};
+                       slab_lds, num_cus};
     return tc::launch_batch(bl, st);
   }
 
@@ -841,6 +855,7 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
     return hip_fail(e, "hipGetDeviceProperties");
   }
   b->num_cus = prop.multiProcessorCount;
+  if (prop.maxSharedMemoryPerMultiProcessor > 0) b->lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
   b->items.resize(n);
   b->analyses.resize(n);
   std::vector<int64_t> host;

@@ -249,6 +249,20 @@ size_t batch_lds_bytes(int config, int slab_lds_doubles) {
   return (size_t)(g > slab_lds_doubles ? g : slab_lds_doubles) * sizeof(double);
 }
 
+int batch_blocks_per_cu(int config) {
+  int n = 0;
+  const size_t lds = batch_lds_bytes(config, kBatchSlabLdsDoubles);
+  hipError_t e = hipErrorInvalidValue;
+  switch (config) {
+#define TC_BCFG(id, bm, bn, bk) \
+  case id: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<bm, bn, bk>, 256, lds); break;
+    TC_BATCH_TILES(TC_BCFG)
+#undef TC_BCFG
+    default: break;
+  }
+  return e == hipSuccess ? n : 0;
+}
+
 hipError_t launch_batch(const BatchLaunch& bl, hipStream_t s) {
   if (bl.ntasks == 0) return hipSuccess;
   switch (bl.config) {

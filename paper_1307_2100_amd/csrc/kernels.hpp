@@ -224,7 +224,8 @@ hipError_t launch_batched_small(const BatchedParams& bp, hipStream_t s);
 constexpr int kNumBatchTiles = 6;
 constexpr int kBatchTileBM[kNumBatchTiles] = {64, 32, 32, 64, 32, 64};
 constexpr int kBatchTileBN[kNumBatchTiles] = {64, 32, 32, 64, 32, 64};
-constexpr int kBatchSlabLdsDoubles = 2048;  // slab LDS of batch tasks (16 KB)
+constexpr int kBatchSlabLdsDoubles = 2048;     // slab LDS of batch tasks: at least 16 KB ...
+constexpr int kBatchSlabLdsMaxDoubles = 8192;  // ... and at most 64 KB, whatever the kernel's occupancy leaves
 // Task kinds of the batch kernel.
 enum BatchKind {
   kBatchGemm = 0,        // one GEMM tile (or one contracted segment of it)
@@ -273,6 +274,9 @@ struct BatchLaunch {
   int num_cus;
 };
 size_t batch_lds_bytes(int config, int slab_lds_doubles);
+// Workgroups of the batch kernel of a tile configuration one CU holds at once
+// (registers and the configuration's own LDS), or 0 on error.
+int batch_blocks_per_cu(int config);
 hipError_t launch_batch(const BatchLaunch& bl, hipStream_t s);
 
 // The picker's MLP (n_in -> hidden -> hidden -> n_out, ReLU, FP32).

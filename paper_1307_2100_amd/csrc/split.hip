@@ -13,9 +13,10 @@
 //     Products of one "level" g = s + t carry the same power of two.  Every
 //     digit product is an integer below 2^(2b), so sums of a few hundred of
 //     them are exact in FP32: the sums of levels 0, 1 and 2 are kept in their
-//     own FP32 accumulators and moved to FP64 every 64 contracted indices,
-//     which keeps them exact; the deeper levels (2^-27 and below) share one
-//     FP32 accumulator whose rounding is far below the target accuracy.
+//     own FP32 accumulators and moved to FP64 before they could round (level
+//     g after 256 / (g + 1) contracted indices), which keeps them exact; the
+//     deeper levels (2^-27 and below) share one FP32 accumulator, moved every
+//     64 indices, whose rounding is far below the target accuracy.
 //   * BF16 planes are stored pre-scaled by 2^(-9(s-1)), so that every product
 //     of planes s and t carries the same factor 2^(-34) sigma_m tau_n; the FP8
 //     planes keep the raw digits and pass the per-plane powers of two as the
@@ -134,27 +135,45 @@ __global__ __launch_bounds__(256) void split_planes_kernel(const double* __restr
   __syncthreads();
   constexpr double first = FP8 ? 16.0 : 256.0;   // 2^b
   constexpr double next = FP8 ? 32.0 : 512.0;    // 2^(b+1)
-  const int kk = tid & 63;
-#pragma unroll 2
-  for (int i = 0; i < 16; ++i) {
-    const int rr = (tid >> 6) + 4 * i;
-    const int64_t r = r0 + rr, k = k0 + kk;
-    if (r >= Rp || k >= Kp) continue;
+  // digit-interleaved layout [r][k / KB][s][k % KB]: one k-step of a row
+  // holds all S digits contiguously (whole cache lines per load).  A thread
+  // takes V consecutive k of one row and writes each digit plane's V entries
+  // as one 16-byte store.
+  constexpr int KB = FP8 ? 128 : 32;
+  constexpr int V = FP8 ? 16 : 8;             // entries per 16 bytes
+  constexpr int GROUPS = 64 / V;              // k groups per tile row
+  for (int item = tid; item < 64 * GROUPS; item += 256) {
+    const int rr = item / GROUPS, kk0 = (item % GROUPS) * V;
+    const int64_t r = r0 + rr, k = k0 + kk0;
+    if (r >= Rp || k >= Kp) continue;  // Kp is a multiple of KB, so all V entries are in range
     const double sg = sigma[r];
-    double rem = sg > 0.0 ? tile[rr][kk] / sg : 0.0;  // exact: sg is a power of two
-    // digit-interleaved layout [r][k / KB][s][k % KB]: one k-step of a row
-    // holds all S digits contiguously (whole cache lines per load)
-    constexpr int KB = FP8 ? 128 : 32;
+    double rem[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) rem[v] = sg > 0.0 ? tile[rr][kk0 + v] / sg : 0.0;  // exact: sg is a power of two
     const int64_t base = r * Kp * S + (k / KB) * (S * KB) + (k % KB);
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const double y = rem * (s == 0 ? first : next);
-      const double q = rint(y);
-      rem = y - q;  // exact
+    for (int s_ = 0; s_ < S; ++s_) {
+      u32x4 word = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double y = rem[v] * (s_ == 0 ? first : next);
+        const double q = rint(y);
+        rem[v] = y - q;  // exact
+        unsigned bits;
+        int shift;
+        if constexpr (FP8) {
+          bits = e4m3_of_small_int((int)q);
+          shift = 8 * (v & 3);
+        } else {
+          bits = bf16_bits_of_small_int(q, -9 * (s_ - 1));
+          shift = 16 * (v & 1);
+        }
+        word[v / (V / 4)] |= bits << shift;
+      }
       if constexpr (FP8) {
-        ((unsigned char*)planes)[base + s * KB] = e4m3_of_small_int((int)q);
+        *reinterpret_cast<u32x4*>((unsigned char*)planes + base + s_ * KB) = word;
       } else {
-        ((u16*)planes)[base + s * KB] = bf16_bits_of_small_int(q, -9 * (s - 1));
+        *reinterpret_cast<u32x4*>((u16*)planes + base + s_ * KB) = word;
       }
     }
   }
@@ -276,21 +295,22 @@ __global__ __launch_bounds__(64 * WGM * WGN) void split_gemm_bf16_kernel(SplitGe
             acc[g][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s_][i], bfr[j], acc[g][i][j], 0, 0, 0);
       }
     }
-    // move the FP32 sums to FP64 every 64 contracted indices (and at the end)
-    if ((ks & 1) == 1 || ks + 1 == ksteps) {
+    // Move FP32 level sums to FP64 before they could round: level g adds
+    // g + 1 digit products below 2^16 per contracted index, so it stays exact
+    // for 256 / (g + 1) indices: level 0 every 256 (8 k-steps), level 1 every
+    // 128, level 2 every 64; the shared deeper levels every 64 as well.
+    const bool last_step = ks + 1 == ksteps;
+#pragma unroll
+    for (int g = 0; g < NACC; ++g) {
+      const int every = g == 0 ? 8 : (g == 1 ? 4 : 2);
+      if (((ks + 1) % every) != 0 && !last_step) continue;
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            double v = 0.0;
-#pragma unroll
-            for (int g = NACC - 1; g >= 0; --g) v += (double)acc[g][i][j][r];
-            acc64[i][j][r] += v;
-          }
-#pragma unroll
-          for (int g = 0; g < NACC; ++g) acc[g][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[g][i][j][r];
+          acc[g][i][j] = f4{0.f, 0.f, 0.f, 0.f};
         }
     }
     if (ks + 1 < ksteps) stg.store(sm[cur ^ 1], tid);
