@@ -108,17 +108,24 @@ __global__ __launch_bounds__(256) void lanes_over_k_kernel(GettParams p, int64_t
   }
 }
 
-// Second pass: output o adds its seg partial sums in segment order.
+// Second pass: output o (one workgroup) adds its seg partial sums.  Thread t
+// takes segments t, t+256, ... in order, then a fixed LDS tree combines the
+// 256 sums, so the result does not depend on timing.
 __global__ __launch_bounds__(256) void sum_partials_kernel(GettParams p, int64_t outputs, int64_t seg,
                                                            const double* __restrict__ part) {
-  const int lane = threadIdx.x & 63;
-  const int64_t o = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  __shared__ double red[256];
+  const int64_t o = blockIdx.x;
   if (o >= outputs) return;
-  // lanes take segments lane, lane+64, ...; the reduction tree is fixed
   double acc = 0.0;
-  for (int64_t s = lane; s < seg; s += 64) acc += part[o * seg + s];
-  const double v = wave_sum(acc);
-  if (lane != 0) return;
+  for (int64_t s = threadIdx.x; s < seg; s += 256) acc += part[o * seg + s];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double v = red[0];
   const int64_t m = o % p.M;
   const int64_t r = o / p.M;
   const int64_t n = r % p.N;
@@ -166,8 +173,8 @@ hipError_t launch_lanes_over_k(const GettParams& p, int64_t seg, double* part, h
   hipLaunchKernelGGL(lanes_over_k_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, outputs, seg, seg_len, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || seg == 1) return e;
-  const int64_t rblocks = (outputs + 3) / 4;
-  hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)rblocks), dim3(256), 0, s, p, outputs, seg, part);
+  if (outputs > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)outputs), dim3(256), 0, s, p, outputs, seg, part);
   return hipGetLastError();
 }
 
