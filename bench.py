@@ -90,12 +90,14 @@ def main():
     torch.cuda.set_device(dev)
 
     if args.copy_calibration:
-        # a plain copy of known size: 1 GiB read, 1 GiB written
+        # plain copies of known size, 1 GiB read and 1 GiB written each: the
+        # runtime's buffer copy, then an elementwise kernel (y = -x)
         x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
         y.copy_(x)
+        torch.neg(x, out=y)
         torch.cuda.synchronize()
-        print("[bench] calibration copy: %d bytes read, %d bytes written" % (x.numel() * 8, y.numel() * 8),
+        print("[bench] calibration copies: %d bytes read, %d bytes written each" % (x.numel() * 8, y.numel() * 8),
               file=sys.stderr, flush=True)
         del x, y
         torch.cuda.empty_cache()
