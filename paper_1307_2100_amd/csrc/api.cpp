@@ -1142,11 +1142,15 @@ tc_status tc_plan_autotune(tc_plan_t plan, const double* A, const double* B, dou
     if (candidate_ms) candidate_ms[c] = -1.0;
     if (!cand[c]) continue;
     float t1 = 0.f, t[3] = {0.f, 0.f, 0.f};
-    result = timed(cand[c], 1, &t1);  // warm-up, and an estimate of the time
-    if (result != TC_OK) break;
+    // a candidate that cannot run on this shape (an error status, not a
+    // device fault) is skipped; a failing stream ends the tuning
+    tc_status cs = timed(cand[c], 1, &t1);  // warm-up, and an estimate of the time
     const int reps = (int)std::min(64.0, std::max(1.0, std::ceil(0.2 / std::max(t1, 1e-4f))));
-    for (int r = 0; r < 3 && result == TC_OK; ++r) result = timed(cand[c], reps, &t[r]);
-    if (result != TC_OK) break;
+    for (int r = 0; r < 3 && cs == TC_OK; ++r) cs = timed(cand[c], reps, &t[r]);
+    if (cs != TC_OK) {
+      if (hipStreamSynchronize(st) != hipSuccess) result = fail(TC_ERR_HIP, "stream failed during autotune");
+      continue;
+    }
     std::sort(t, t + 3);
     if (candidate_ms) candidate_ms[c] = t[1];
     if (best < 0 || t[1] < best_t) {

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void batched_small_kernel(BatchedParams bp) {
 hipError_t launch_batched_small(const BatchedParams& bp, hipStream_t s) {
   if (bp.L == 0) return hipSuccess;
   const int64_t blocks = (bp.L + bp.P - 1) / bp.P;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (blocks > 0xffffffffLL / 256) return hipErrorInvalidConfiguration;  // total threads below 2^32
   const size_t lds = (size_t)bp.P * (bp.a.size + bp.b.size + bp.c.size) * sizeof(double) + 2 * sizeof(int) * bp.K;
   hipLaunchKernelGGL(batched_small_kernel, dim3((unsigned)blocks), dim3(256), lds, s, bp);
   return hipGetLastError();

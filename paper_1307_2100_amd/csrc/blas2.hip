@@ -14,6 +14,8 @@
 //    outputs exist, the contracted range is cut into segments whose partial
 //    sums go to the workspace and a second pass adds them in a fixed order
 //    (deterministic).
+#include <algorithm>
+
 #include "lanes.hpp"
 
 namespace tc {
@@ -25,55 +27,58 @@ namespace {
 __global__ __launch_bounds__(256) void lanes_over_outputs_kernel(GettParams p, int n_fastest, int64_t total,
                                                                  int64_t seg, int64_t seg_len,
                                                                  double* __restrict__ part) {
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= total) return;
-  int64_t m, n, l;
-  if (n_fastest) {
-    n = o % p.N;
-    const int64_t r = o / p.N;
-    m = r % p.M;
-    l = r / p.M;
-  } else {
-    m = o % p.M;
-    const int64_t r = o / p.M;
-    n = r % p.N;
-    l = r / p.N;
-  }
-  const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
-  const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
   const int64_t s = blockIdx.y;
   const int64_t k0 = s * seg_len;
   const int64_t k1 = k0 + seg_len < p.K ? k0 + seg_len : p.K;
-  const double v = lanes_out_dot(A, B, p.aK, p.bK, k0, k1);
-  if (seg > 1) {
-    part[s * total + o] = v;
-    return;
+  // grid-stride over the outputs: any output count fits the grid limits
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    int64_t m, n, l;
+    if (n_fastest) {
+      n = o % p.N;
+      const int64_t r = o / p.N;
+      m = r % p.M;
+      l = r / p.M;
+    } else {
+      m = o % p.M;
+      const int64_t r = o / p.M;
+      n = r % p.N;
+      l = r / p.N;
+    }
+    const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
+    const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
+    const double v = lanes_out_dot(A, B, p.aK, p.bK, k0, k1);
+    if (seg > 1) {
+      part[s * total + o] = v;
+      continue;
+    }
+    double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
+    *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
   }
-  double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
-  *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
 }
 
 // Second pass of the segmented form: output o adds its partial sums in segment order.
 __global__ __launch_bounds__(256) void sum_out_partials_kernel(GettParams p, int n_fastest, int64_t total,
                                                                int64_t seg, const double* __restrict__ part) {
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= total) return;
-  double v = 0.0;
-  for (int64_t s = 0; s < seg; ++s) v += part[s * total + o];
-  int64_t m, n, l;
-  if (n_fastest) {
-    n = o % p.N;
-    const int64_t r = o / p.N;
-    m = r % p.M;
-    l = r / p.M;
-  } else {
-    m = o % p.M;
-    const int64_t r = o / p.M;
-    n = r % p.N;
-    l = r / p.N;
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int64_t s = 0; s < seg; ++s) v += part[s * total + o];
+    int64_t m, n, l;
+    if (n_fastest) {
+      n = o % p.N;
+      const int64_t r = o / p.N;
+      m = r % p.M;
+      l = r / p.M;
+    } else {
+      m = o % p.M;
+      const int64_t r = o / p.M;
+      n = r % p.N;
+      l = r / p.N;
+    }
+    double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
+    *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
   }
-  double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
-  *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -87,24 +92,26 @@ __device__ inline double wave_sum(double v) {
 __global__ __launch_bounds__(256) void lanes_over_k_kernel(GettParams p, int64_t outputs, int64_t seg,
                                                            int64_t seg_len, double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (w >= outputs * seg) return;
-  const int64_t o = w / seg, s = w % seg;
-  const int64_t m = o % p.M;
-  const int64_t r = o / p.M;
-  const int64_t n = r % p.N;
-  const int64_t l = r / p.N;
-  const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
-  const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
-  const int64_t k0 = s * seg_len;
-  const int64_t k1 = k0 + seg_len < p.K ? k0 + seg_len : p.K;
-  const double v = wave_sum(lanes_k_dot(A, B, p.aK, p.bK, k0, k1, lane));
-  if (lane != 0) return;
-  if (seg == 1) {
-    double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
-    *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
-  } else {
-    part[o * seg + s] = v;
+  const int64_t waves = outputs * seg, stride = (int64_t)gridDim.x * (blockDim.x / 64);
+  // grid-stride over (output, segment) pairs, uniform per wavefront
+  for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); w < waves; w += stride) {
+    const int64_t o = w / seg, s = w % seg;
+    const int64_t m = o % p.M;
+    const int64_t r = o / p.M;
+    const int64_t n = r % p.N;
+    const int64_t l = r / p.N;
+    const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
+    const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
+    const int64_t k0 = s * seg_len;
+    const int64_t k1 = k0 + seg_len < p.K ? k0 + seg_len : p.K;
+    const double v = wave_sum(lanes_k_dot(A, B, p.aK, p.bK, k0, k1, lane));
+    if (lane != 0) continue;
+    if (seg == 1) {
+      double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
+      *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
+    } else {
+      part[o * seg + s] = v;
+    }
   }
 }
 
@@ -140,8 +147,8 @@ hipError_t launch_lanes_over_outputs(const GettParams& p, bool n_fastest, int64_
   const int64_t total = p.M * p.N * p.L;
   if (total == 0) return hipSuccess;
   if (seg < 1 || !part) seg = 1;
-  const int64_t blocks = (total + 255) / 256;
-  if (blocks > 0x7fffffffLL || seg > 65535) return hipErrorInvalidConfiguration;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, kMaxGridBlocks);
+  if (seg > 65535) return hipErrorInvalidConfiguration;
   const int64_t seg_len = (p.K + seg - 1) / seg;
   hipLaunchKernelGGL(lanes_over_outputs_kernel, dim3((unsigned)blocks, (unsigned)seg), dim3(256), 0, s, p,
                      n_fastest ? 1 : 0, total, seg, seg_len, part);
@@ -168,8 +175,7 @@ hipError_t launch_lanes_over_k(const GettParams& p, int64_t seg, double* part, h
   if (seg < 1) seg = 1;
   const int64_t seg_len = (p.K + seg - 1) / seg;
   const int64_t waves = outputs * seg;
-  const int64_t blocks = (waves + 3) / 4;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  const int64_t blocks = std::min<int64_t>((waves + 3) / 4, kMaxGridBlocks);
   hipLaunchKernelGGL(lanes_over_k_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, outputs, seg, seg_len, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || seg == 1) return e;

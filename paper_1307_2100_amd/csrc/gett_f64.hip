@@ -82,7 +82,8 @@ hipError_t launch_cfg(const GettParams& p, bool akf, bool bkf, int S, int64_t se
   const int64_t tilesM = (p.M + BM - 1) / BM, tilesN = (p.N + BN - 1) / BN;
   const int64_t total = tilesM * tilesN * p.L;
   if (total == 0) return hipSuccess;
-  if (total * S > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  // a grid's total thread count must stay below 2^32
+  if (total * S > 0xffffffffLL / (64 * WGM * WGN)) return hipErrorInvalidConfiguration;
   dim3 block(64 * WGM * WGN);
   if (S > 1) {
     dim3 grid((unsigned)(total * S));

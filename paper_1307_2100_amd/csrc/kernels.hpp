@@ -6,6 +6,10 @@
 
 #include <cstdint>
 
+// Grid-stride kernels launch at most this many workgroups (a grid's total
+// thread count must stay below 2^32).
+constexpr int64_t kMaxGridBlocks = 1 << 20;
+
 // Device helpers are always inlined: a real call would cost the calling
 // kernel its register budget (the callee cannot share the caller's).
 #define TC_DEV __device__ __attribute__((always_inline)) inline

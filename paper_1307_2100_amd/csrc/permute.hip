@@ -6,6 +6,8 @@
 // transposition happening in LDS.  Unlike the paper's slice-by-slice copy,
 // the whole operand is reordered in one pass, so every byte is read once and
 // written once (its footnote on amortising the copy over all slices).
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace tc {
@@ -56,28 +58,28 @@ __global__ __launch_bounds__(256) void permute_tile_kernel(PermPlan p) {
 
 // X and Y share their fastest mode: plain strided copy, one element per thread.
 __global__ __launch_bounds__(256) void permute_flat_kernel(PermuteParams p, int64_t total) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  int64_t ox = 0, oy = 0;
-  for (int d = 0; d < p.rank; ++d) {
-    int64_t v = i % p.ext[d];
-    i /= p.ext[d];
-    ox += v * p.sx[d];
-    oy += v * p.sy[d];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = e, ox = 0, oy = 0;
+    for (int d = 0; d < p.rank; ++d) {
+      int64_t v = i % p.ext[d];
+      i /= p.ext[d];
+      ox += v * p.sx[d];
+      oy += v * p.sy[d];
+    }
+    p.Y[oy] = p.X[ox];
   }
-  p.Y[oy] = p.X[ox];
 }
 
 __global__ __launch_bounds__(256) void scale_kernel(double* C, Offs cM, Offs cN, Offs cL, int64_t M, int64_t N,
                                                     int64_t total, double beta) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  int64_t n = i % N;
-  int64_t r = i / N;
-  int64_t m = r % M;
-  int64_t l = r / M;
-  double* d = C + off_at(cM, m) + off_at(cN, n) + off_at(cL, l);
-  *d = beta == 0.0 ? 0.0 : beta * *d;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t n = i % N;
+    int64_t r = i / N;
+    int64_t m = r % M;
+    int64_t l = r / M;
+    double* d = C + off_at(cM, m) + off_at(cN, n) + off_at(cL, l);
+    *d = beta == 0.0 ? 0.0 : beta * *d;
+  }
 }
 
 }  // namespace
@@ -101,7 +103,7 @@ hipError_t launch_permute(const PermuteParams& p, hipStream_t s) {
       std::swap(q.sx[0], q.sx[a]);
       std::swap(q.sy[0], q.sy[a]);
     }
-    int64_t blocks = (total + 255) / 256;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, kMaxGridBlocks);
     hipLaunchKernelGGL(permute_flat_kernel, dim3((unsigned)blocks), dim3(256), 0, s, q, total);
     return hipGetLastError();
   }
@@ -126,7 +128,7 @@ hipError_t launch_permute(const PermuteParams& p, hipStream_t s) {
     outer *= p.ext[d];
   }
   int64_t blocks = pp.ta * pp.tb * outer;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (blocks > 0xffffffffLL / 256) return hipErrorInvalidConfiguration;  // total threads below 2^32
   hipLaunchKernelGGL(permute_tile_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pp);
   return hipGetLastError();
 }
@@ -135,7 +137,7 @@ hipError_t launch_scale(double* C, Offs cM, Offs cN, Offs cL, int64_t M, int64_t
                         hipStream_t s) {
   int64_t total = M * N * L;
   if (total == 0) return hipSuccess;
-  int64_t blocks = (total + 255) / 256;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, kMaxGridBlocks);
   hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blocks), dim3(256), 0, s, C, cM, cN, cL, M, N, total, beta);
   return hipGetLastError();
 }

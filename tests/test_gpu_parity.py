@@ -197,3 +197,27 @@ def test_split_k_is_used_and_exact():
         got, info = _run(labA, labB, labC, A, B, recipe)
         assert info["k_split"] > 1, info
         assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
+
+
+def test_grid_stride_over_huge_output_counts():
+    """DOT recipe forced on a grid contraction with 70M outputs: more
+    (output, segment) wavefronts than one grid holds, so the lanes kernel walks
+    them grid-stride; sampled outputs against the oracle (bit-exact on integers)."""
+    ext = {"a": 4, "b": 4, "c": 4, "d": 4, "x": 1100000}
+    labA, labB, labC = "abdx", "dcx", "abcx"
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(31)
+    dA = torch.randint(-4, 5, [ext[l] for l in reversed(labA)], generator=gen, device="cuda").double().permute(3, 2, 1, 0)
+    dB = torch.randint(-4, 5, [ext[l] for l in reversed(labB)], generator=gen, device="cuda").double().permute(2, 1, 0)
+    C = colmajor_zeros([ext[l] for l in labC])
+    plan = tc.Plan.for_tensors(dA, labA, dB, labB, C, labC, recipe="dot")
+    assert plan.info.kernel == 2 and plan.info.M * plan.info.N * plan.info.L > (1 << 26)
+    plan.execute(dA, dB, C)
+    torch.cuda.synchronize()
+    plan.close()
+    g = np.random.default_rng(3)
+    idx = np.stack([g.integers(0, ext[l], 400) for l in labC], axis=1)
+    idx[:8, 3] = ext["x"] - 1 - np.arange(8)            # include the last points
+    s, _ = oracle.contract_entries(dA.cpu().numpy(), labA, dB.cpu().numpy(), labB, labC, idx)
+    got = C.cpu().numpy()[tuple(idx.T)]
+    assert np.array_equal(got, s)
