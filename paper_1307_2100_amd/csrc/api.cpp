@@ -407,8 +407,6 @@ struct tc_batch_s {
         // memory-bound: groups of outputs; long contracted ranges in segments
         const bool lk = it.kind == tc::kBatchLanesK;
         const int64_t outputs = it.g.M * it.g.N * it.g.L;
-        const int64_t per = lk ? tc::kLanesKOutputs : tc::kLanesOutOutputs;
-        const int64_t groups = (outputs + per - 1) / per;
         const int64_t target = lk ? 16384 : 512;  // contracted indices per segment
         int S = 1;
         int64_t len = it.g.K;
@@ -420,13 +418,27 @@ struct tc_batch_s {
         it.seg_len = len;
         it.part_off = S > 1 ? n_parts : 0;
         it.cnt_off = S > 1 ? n_cnt : 0;
-        if (S > 1) {
-          n_parts += outputs * S;
-          n_cnt += groups;
+        if (lk) {
+          // four (output, segment) units per task, one per wavefront; one
+          // completion counter per output
+          if (S > 1) {
+            n_parts += outputs * S;
+            n_cnt += outputs;
+          }
+          const int64_t ntask = (outputs * S + tc::kLanesKOutputs - 1) / tc::kLanesKOutputs;
+          const double cost = 16.0 * tc::kLanesKOutputs * (double)len / 8e12;
+          for (int64_t t = 0; t < ntask; ++t) tasks.push_back({cost, tc::BatchTask{i, 0, t}});
+        } else {
+          // 256 outputs along lanes per task, one task per (output group, segment)
+          const int64_t groups = (outputs + tc::kLanesOutOutputs - 1) / tc::kLanesOutOutputs;
+          if (S > 1) {
+            n_parts += outputs * S;
+            n_cnt += groups;
+          }
+          const double cost = 16.0 * tc::kLanesOutOutputs * (double)len / 8e12;
+          for (int64_t t = 0; t < groups; ++t)
+            for (int sg = 0; sg < S; ++sg) tasks.push_back({cost, tc::BatchTask{i, sg, t}});
         }
-        const double cost = 16.0 * (double)per * (double)len / 8e12;
-        for (int64_t t = 0; t < groups; ++t)
-          for (int sg = 0; sg < S; ++sg) tasks.push_back({cost, tc::BatchTask{i, sg, t}});
       } else if (it.kind == tc::kBatchGemm) {
         it.tilesM = (it.g.M + BM - 1) / BM;
         it.tilesN = (it.g.N + BN - 1) / BN;

@@ -55,40 +55,46 @@ TC_DEV void batch_store(const GettParams& p, int64_t m, int64_t n, int64_t l, do
   *dst = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *dst;
 }
 
-// Lanes over k: wavefront w of the workgroup takes output 4 idx + w and
-// contracted segment seg; lanes stride along k.
+// Lanes over k: the (output, contracted segment) units of the item are
+// numbered u = o * S + s, and wavefront w of the workgroup takes unit
+// 4 idx + w (so the four wavefronts share an output's segments when outputs
+// are few).  Lanes stride along k.  With S > 1 each wavefront stores its
+// partial sum and counts its output's finished segments; the wavefront that
+// finishes the last one adds the S partial sums in a fixed order.
 TC_DEV void batch_lanes_k(const BatchItem& it, const GettParams& p, const BatchTask& task,
-                                     double* __restrict__ parts, unsigned* __restrict__ tile_cnt, int* last) {
+                          double* __restrict__ parts, unsigned* __restrict__ tile_cnt) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t outputs = p.M * p.N * p.L;
-  const int64_t o = task.idx * kLanesKOutputs + wave;
   const int S = it.ksplit;
-  int64_t m = 0, n = 0, l = 0;
-  double v = 0.0;
-  if (o < outputs) {  // uniform per wavefront
-    m = o % p.M;
-    const int64_t r = o / p.M;
-    n = r % p.N;
-    l = r / p.N;
-    const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
-    const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
-    const int64_t k0 = (int64_t)task.seg * it.seg_len;
-    const int64_t k1 = k0 + it.seg_len < p.K ? k0 + it.seg_len : p.K;
-    v = batch_wave_sum(lanes_k_dot(A, B, p.aK, p.bK, k0, k1, lane));
-  }
+  const int64_t u = task.idx * kLanesKOutputs + wave;
+  if (u >= outputs * S) return;  // uniform per wavefront; no workgroup barrier follows
+  const int64_t o = u / S;
+  const int s = (int)(u - o * S);
+  const int64_t m = o % p.M;
+  const int64_t r = o / p.M;
+  const int64_t n = r % p.N;
+  const int64_t l = r / p.N;
+  const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
+  const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
+  const int64_t k0 = (int64_t)s * it.seg_len;
+  const int64_t k1 = k0 + it.seg_len < p.K ? k0 + it.seg_len : p.K;
+  const double v = batch_wave_sum(lanes_k_dot<8>(A, B, p.aK, p.bK, k0, k1, lane));
   if (S == 1) {
-    if (o < outputs && lane == 0) batch_store(p, m, n, l, v);
+    if (lane == 0) batch_store(p, m, n, l, v);
     return;
   }
-  if (o < outputs && lane == 0) parts[it.part_off + o * S + task.seg] = v;
-  if (!batch_last_segment(&tile_cnt[it.cnt_off + task.idx], S, last)) return;
-  if (o < outputs) {
-    // segments in a fixed order: lane-strided, then the fixed reduction tree
-    double acc = 0.0;
-    for (int sg = lane; sg < S; sg += 64) acc += parts[it.part_off + o * S + sg];
-    acc = batch_wave_sum(acc);
-    if (lane == 0) batch_store(p, m, n, l, acc);
-  }
+  if (lane == 0) parts[it.part_off + o * S + s] = v;
+  __threadfence();
+  int last = 0;
+  if (lane == 0) last = atomicAdd(&tile_cnt[it.cnt_off + o], 1u) == (unsigned)(S - 1);
+  last = __shfl(last, 0, 64);
+  if (!last) return;
+  __threadfence();
+  // segments in a fixed order: lane-strided, then the fixed reduction tree
+  double acc = 0.0;
+  for (int sg = lane; sg < S; sg += 64) acc += parts[it.part_off + o * S + sg];
+  acc = batch_wave_sum(acc);
+  if (lane == 0) batch_store(p, m, n, l, acc);
 }
 
 // Lanes over outputs: thread t takes output 256 idx + t (n or m fastest
@@ -168,7 +174,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict_
       p.alpha = pt.alpha;
       p.beta = pt.beta;
       if (it.kind == kBatchLanesK)
-        batch_lanes_k(it, p, task, parts, tile_cnt, &last);
+        batch_lanes_k(it, p, task, parts, tile_cnt);
       else
         batch_lanes_out(it, p, task, parts, tile_cnt, &last);
     } else if (it.kind == kBatchGemm) {

@@ -234,10 +234,10 @@ constexpr int kBatchSlabLdsMaxDoubles = 8192;  // ... and at most 64 KB, whateve
 enum BatchKind {
   kBatchGemm = 0,        // one GEMM tile (or one contracted segment of it)
   kBatchSlab = 1,        // the slabs of P batch indices
-  kBatchLanesK = 2,      // 4 outputs, one wavefront each, lanes along the contracted index
+  kBatchLanesK = 2,      // 4 (output, segment) units, one wavefront each, lanes along the contracted index
   kBatchLanesOut = 3     // 256 outputs along lanes, each walking one contracted segment
 };
-constexpr int kLanesKOutputs = 4;      // outputs per lanes-over-k task (one per wavefront)
+constexpr int kLanesKOutputs = 4;      // (output, segment) units per lanes-over-k task (one per wavefront)
 constexpr int kLanesOutOutputs = 256;  // outputs per lanes-over-outputs task (one per thread)
 struct BatchItem {       // one contraction of a batch (layout only)
   GettParams g;          // kinds 0, 2, 3

@@ -12,7 +12,10 @@
 namespace tc {
 
 // Lanes along k: this lane's share of sum_k A[aK(k)] B[bK(k)] over
-// k = k0 + lane, k0 + lane + 64, ... below k1 (four independent sums).
+// k = k0 + lane, k0 + lane + 64, ... below k1.  U strided elements of each
+// operand are in flight per step (U independent sums); kernels with registers
+// to spare take U = 8.
+template <int U = 4>
 TC_DEV double lanes_k_dot(const double* __restrict__ A, const double* __restrict__ B, const Offs& aK,
                           const Offs& bK, int64_t k0, int64_t k1, int lane) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -42,31 +45,38 @@ TC_DEV double lanes_k_dot(const double* __restrict__ A, const double* __restrict
     if (((k1 - k0) & 1) && lane == 0) acc[1] += A[k1 - 1] * B[k1 - 1];
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
   }
-  int64_t oa[4], ob[4];
+  double accu[U];
+  int64_t oa[U], ob[U];
   int64_t k = k0 + lane;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < U; ++u) {
+    accu[u] = 0.0;
     const int64_t kk = k + 64 * u;
     oa[u] = kk < k1 ? off_at(aK, kk) : -1;
     ob[u] = kk < k1 ? off_at(bK, kk) : -1;
   }
-  for (; k < k1; k += 256) {
-    double a[4], b[4];
+  for (; k < k1; k += 64 * U) {
+    double a[U], b[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       a[u] = oa[u] >= 0 ? A[oa[u]] : 0.0;
       b[u] = ob[u] >= 0 ? B[ob[u]] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t kk = k + 256 + 64 * u;
+    for (int u = 0; u < U; ++u) {
+      const int64_t kk = k + 64 * U + 64 * u;
       oa[u] = kk < k1 ? off_at(aK, kk) : -1;
       ob[u] = kk < k1 ? off_at(bK, kk) : -1;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] += a[u] * b[u];
+    for (int u = 0; u < U; ++u) accu[u] += a[u] * b[u];
   }
-  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  // pairwise in a fixed order
+#pragma unroll
+  for (int w = U / 2; w >= 1; w /= 2)
+#pragma unroll
+    for (int u = 0; u < w; ++u) accu[u] += accu[u + w];
+  return accu[0];
 }
 
 // One output per thread: sum_k A[aK(k)] B[bK(k)] over k in [k0, k1) in order
