@@ -241,13 +241,18 @@ struct Picker {
   std::vector<float> mean, stdev;
   float* d_in = nullptr;
   float* d_out = nullptr;
+  // private non-blocking stream: a prediction at plan time does not wait for
+  // the caller's queued work
+  hipStream_t stream = nullptr;
   std::map<std::string, int> tune;  // shape signature -> candidate
   void drop() {
     delete net;
     net = nullptr;
     if (d_in) (void)hipFree(d_in);
     if (d_out) (void)hipFree(d_out);
+    if (stream) (void)hipStreamDestroy(stream);
     d_in = d_out = nullptr;
+    stream = nullptr;
   }
 };
 Picker g_picker;
@@ -264,10 +269,12 @@ std::vector<int> picker_order(const float* feat) {
   for (int i = 0; i < TC_PICKER_FEATURES; ++i)
     x[i] = (feat[i] - g_picker.mean[i]) / (g_picker.stdev[i] > 0.f ? g_picker.stdev[i] : 1.f);
   tc_mlp_s* n = g_picker.net;
-  if (hipMemcpy(g_picker.d_in, x, sizeof(x), hipMemcpyHostToDevice) != hipSuccess) return order;
-  if (tc::mlp_forward(n->d, n->params, g_picker.d_in, n->w.H1, n->w.H2, g_picker.d_out, 1, nullptr) != hipSuccess)
+  hipStream_t st = g_picker.stream;
+  if (hipMemcpyAsync(g_picker.d_in, x, sizeof(x), hipMemcpyHostToDevice, st) != hipSuccess) return order;
+  if (tc::mlp_forward(n->d, n->params, g_picker.d_in, n->w.H1, n->w.H2, g_picker.d_out, 1, st) != hipSuccess)
     return order;
-  if (hipMemcpy(y, g_picker.d_out, sizeof(y), hipMemcpyDeviceToHost) != hipSuccess) return order;
+  if (hipMemcpyAsync(y, g_picker.d_out, sizeof(y), hipMemcpyDeviceToHost, st) != hipSuccess) return order;
+  if (hipStreamSynchronize(st) != hipSuccess) return order;
   for (int c = 0; c < TC_PICKER_CANDIDATES; ++c) order.push_back(c);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return y[a] < y[b]; });
   return order;
@@ -1091,7 +1098,8 @@ tc_status tc_picker_install(const float* params, int64_t n_params, int n_in, int
   g_picker.mean.assign(feat_mean, feat_mean + n_in);
   g_picker.stdev.assign(feat_std, feat_std + n_in);
   if (hipMalloc((void**)&g_picker.d_in, n_in * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&g_picker.d_out, n_out * sizeof(float)) != hipSuccess) {
+      hipMalloc((void**)&g_picker.d_out, n_out * sizeof(float)) != hipSuccess ||
+      hipStreamCreateWithFlags(&g_picker.stream, hipStreamNonBlocking) != hipSuccess) {
     g_picker.drop();
     return fail(TC_ERR_NOMEM, "picker buffers");
   }
