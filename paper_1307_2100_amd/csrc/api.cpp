@@ -749,7 +749,7 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
     return e == hipSuccess ? TC_OK : hip_fail(e, "split-precision launch");
   }
 
-  if (info.recipe == TC_RECIPE_COPY_GEMM && an.copy_slot >= 0) {
+  if (an.copy_slot >= 0) {
     tc::PermuteParams pp{};
     pp.X = an.copy_slot == tc::SA ? KA : KB;
     pp.Y = (double*)workspace;
@@ -901,12 +901,12 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
     o.recipe = TC_RECIPE_AUTO;
     tc::Analysis an;
     std::string err;
-    tc_status s = tc::analyze(p->desc[0], p->desc[1], p->desc[2], o, &an, &err);
+    tc_status s = tc::analyze(p->desc[0], p->desc[1], p->desc[2], o, &an, &err, false);
     const bool keep = an.kernel == tc::Analysis::KERNEL_BATCHED || an.kernel == tc::Analysis::KERNEL_LANES_K ||
                       an.kernel == tc::Analysis::KERNEL_LANES_OUT;
     if (s == TC_OK && !keep) {
       o.recipe = TC_RECIPE_GEMM;
-      s = tc::analyze(p->desc[0], p->desc[1], p->desc[2], o, &an, &err);
+      s = tc::analyze(p->desc[0], p->desc[1], p->desc[2], o, &an, &err, false);
     }
     if (s != TC_OK) {
       delete b;

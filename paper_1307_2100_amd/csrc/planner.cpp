@@ -272,7 +272,7 @@ int paper_class(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, i
 }
 
 tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& C0, const tc_options& opt,
-                  Analysis* out, std::string* err) {
+                  Analysis* out, std::string* err, bool allow_copy) {
   Analysis an;
   const TensorDesc* T[3] = {&A0, &B0, &C0};
   const char* name[3] = {"A", "B", "C"};
@@ -417,6 +417,19 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
   // (Split precision gathers both inputs into digit planes: no copy there.)
   if (recipe == TC_RECIPE_COPY_GEMM && opt.precision == TC_PREC_F64)
     an.copy_slot = an.elems[SA] < an.elems[SB] ? SA : SB;
+  // The inner-product recipes (DOT, and GEMV along k) read both inputs along
+  // the contracted index with consecutive lanes.  When the two stride-1 modes
+  // are different contracted indices (the situation of Class 3.1, failure
+  // F1), one input could only be read with strided lanes, so -- as for
+  // COPY+GEMM -- the smaller input is first copied into the other's
+  // contracted order.
+  if (allow_copy && opt.precision == TC_PREC_F64 && (recipe == TC_RECIPE_DOT || recipe == TC_RECIPE_GEMV) &&
+      !an.empty_out && !an.empty_sum) {
+    const int kua = unit_mode(KA), kub = unit_mode(KB);
+    auto contracted = [&](int32_t l) { return find_label(KA, l) >= 0 && find_label(KB, l) >= 0 && find_label(C, l) < 0; };
+    if (kua >= 0 && kub >= 0 && KA.lab[kua] != KB.lab[kub] && contracted(KA.lab[kua]) && contracted(KB.lab[kub]))
+      an.copy_slot = an.elems[SA] < an.elems[SB] ? SA : SB;
+  }
   info.copy_operand = an.copy_slot < 0 ? -1 : ((an.copy_slot == SA) != swap ? 0 : 1);
 
   order_group(G[GM], SA, SC);

@@ -88,9 +88,11 @@ struct Analysis {
 };
 
 // Validates, classifies (Sec. 3.2) and lays out the contraction.  On error
-// returns the status and writes a message to *err.
+// returns the status and writes a message to *err.  allow_copy = false keeps
+// the inner-product recipes from planning a copy of an input (a batch has no
+// copy pass).
 tc_status analyze(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, const tc_options& opt,
-                  Analysis* out, std::string* err);
+                  Analysis* out, std::string* err, bool allow_copy = true);
 
 // Picker features of an analysis (TC_PICKER_FEATURES floats).
 void picker_features(const Analysis& an, const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, float* f);

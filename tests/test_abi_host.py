@@ -194,6 +194,22 @@ def test_copy_recipe_workspace_and_operand():
     assert analyze("abg", "gah", "bh", ext2).copy_operand == 1
 
 
+def test_inner_products_copy_when_stride1_modes_are_different_contracted_indices():
+    # DOT of A[i,j] and B[j,i]: the stride-1 modes i and j are both contracted
+    # and differ (Class 3.1's failure F1 for a BLAS-1 slice): the smaller
+    # input is copied into the other's contracted order first
+    info = analyze("ij", "ji", "", {"i": 40, "j": 30})
+    assert info.recipe == tc.TC_RECIPE_DOT and info.copy_operand in (0, 1)
+    assert info.workspace_bytes >= 8 * 40 * 30
+    # same order: no copy
+    assert analyze("ij", "ij", "", {"i": 40, "j": 30}).copy_operand == -1
+    # GEMV with the vector in another contracted order: the vector is copied
+    info = analyze("ijm", "ji", "m", {"i": 20, "j": 30, "m": 50})
+    assert info.recipe == tc.TC_RECIPE_GEMV and info.copy_operand >= 0
+    # the vector's stride-1 mode is the matrix's: no copy
+    assert analyze("ijm", "ij", "m", {"i": 20, "j": 30, "m": 50}).copy_operand == -1
+
+
 def test_empty_and_degenerate_shapes_analyze():
     info = analyze("ik", "kj", "ij", {"i": 0, "k": 3, "j": 2})
     assert info.M == 0 and info.flops == 0

@@ -169,6 +169,9 @@ def test_permute_entry_point_bit_exact():
     ("gemv_few_outputs", "abg", "bg", "a", {"a": 3, "b": 2000, "g": 9}),
     # lanes over outputs with few outputs and a long sum: contracted segments, ordered second pass
     ("gemv_n_segments", "abg", "bg", "a", {"a": 700, "b": 60, "g": 50}),
+    # stride-1 modes are different contracted indices: the smaller input is copied first
+    ("dot_mismatch", "ij", "ji", "", {"i": 300, "j": 170}),
+    ("gemv_t_mismatch", "ijm", "ji", "m", {"i": 70, "j": 90, "m": 33}),
 ])
 def test_memory_bound_recipes(case):
     name, labA, labB, labC, ext = case
