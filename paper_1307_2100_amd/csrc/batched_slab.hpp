@@ -115,28 +115,15 @@ TC_DEV void batched_slab(const BatchedParams& bp, const double* __restrict__ A,
   slab_load(A, bp.aL, bp.a, l0, np, P, bp.P_div, As, tid, blockDim.x);
   slab_load(B, bp.bL, bp.b, l0, np, P, bp.P_div, Bs, tid, blockDim.x);
   __syncthreads();
-  // T consecutive lanes per output entry (p, m, n), n fastest: when the
-  // outputs leave threads idle, each of T lanes sums every T-th contracted
-  // index and a fixed butterfly combines the T partial sums
-  const int outs = np * sC;
-  int T = 1;
-  while (T < 8 && 2 * T <= K && outs * 2 * T <= (int)blockDim.x) T *= 2;
-  const int sub = tid & (T - 1);
-  for (int base = tid - sub; base < outs * T; base += blockDim.x) {
-    const int o = base / T;  // uniform across the T lanes of one output
+  // one thread per output entry (p, m, n), n fastest
+  for (int o = tid; o < np * sC; o += blockDim.x) {
+    const uint32_t p = fdiv((uint32_t)o, bp.sC_div), mn = (uint32_t)o - p * (uint32_t)sC;
+    const uint32_t m = fdiv(mn, bp.N_div), n = mn - m * (uint32_t)bp.N;
+    const double* a = As + p * sA + off_at(bp.am, m);
+    const double* b = Bs + p * sB + off_at(bp.bn, n);
     double acc = 0.0;
-    uint32_t p = 0, m = 0, n = 0;
-    if (o < outs) {
-      p = fdiv((uint32_t)o, bp.sC_div);
-      const uint32_t mn = (uint32_t)o - p * (uint32_t)sC;
-      m = fdiv(mn, bp.N_div);
-      n = mn - m * (uint32_t)bp.N;
-      const double* a = As + p * sA + off_at(bp.am, m);
-      const double* b = Bs + p * sB + off_at(bp.bn, n);
-      for (int k = sub; k < K; k += T) acc += a[kA[k]] * b[kB[k]];
-    }
-    for (int w = 1; w < T; w *= 2) acc += __shfl_xor(acc, w, 64);
-    if (o < outs && sub == 0) Cs[p * sC + off_at(bp.cm, m) + off_at(bp.cn, n)] = acc;
+    for (int k = 0; k < K; ++k) acc += a[kA[k]] * b[kB[k]];
+    Cs[p * sC + off_at(bp.cm, m) + off_at(bp.cn, n)] = acc;
   }
   __syncthreads();
   if (bp.c.contig) {
