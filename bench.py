@@ -270,14 +270,15 @@ def time_plan(plan, dA, dB, C, reps, stream):
 
 
 def split_runs(work, reps):
-    """Split-precision (BF16 and FP8 digits) on the same inputs: time (HIP
-    events around each tc_execute, split pass included) and sampled error."""
+    """Split-precision (BF16 and FP8 digits, INT8 residues) on the same inputs:
+    time (HIP events around each tc_execute, split pass included) and sampled
+    error."""
     import torch
 
     import paper_1307_2100_amd as tc
     stream = torch.cuda.current_stream()
     out = {}
-    for prec in ("split_bf16", "split_fp8"):
+    for prec in ("split_bf16", "split_fp8", "crt_int8"):
         res = {}
         for name, w in work.items():
             labA, labB, labC, ext = w["spec"]
@@ -286,7 +287,8 @@ def split_runs(work, reps):
             ms = time_plan(plan, w["dA"], w["dB"], C, reps, stream)
             err = sampled_error(w["A"], labA, w["B"], labB, labC, ext, C)
             res[name] = {"ms": round(ms, 4), "effective_tflops": round(plan.info.flops / ms / 1e9, 3),
-                         "digits": plan.info.split_slices, "max_componentwise_error_sampled": err,
+                         "digits": plan.info.split_slices, "bits": plan.info.split_bits,
+                         "max_componentwise_error_sampled": err,
                          "workspace_gb": round(plan.info.workspace_bytes / 1e9, 3)}
             plan.close()
             del C
@@ -297,7 +299,8 @@ def split_runs(work, reps):
 def precision_runs(args):
     """The precision workload: both coupled-cluster contractions at v=192,
     o=48 with N(0,1) inputs scaled per last-index slice by 10^U(-3,3), in FP64,
-    split BF16 and split FP8, each with its sampled error against the oracle."""
+    split BF16, split FP8 and INT8 residues, each with its sampled error
+    against the oracle."""
     import torch
 
     import paper_1307_2100_amd as tc
@@ -312,16 +315,18 @@ def precision_runs(args):
         dB = torch.from_numpy(B).to(dev)
         C = tc.empty_colmajor([ext[l] for l in labC], device=dev)
         res = {}
-        for prec in ("f64", "split_bf16", "split_fp8"):
+        for prec in ("f64", "split_bf16", "split_fp8", "crt_int8"):
             plan = tc.Plan.for_tensors(dA, labA, dB, labB, C, labC, precision=prec)
             ms = time_plan(plan, dA, dB, C, 3, stream)
             err = sampled_error(A, labA, B, labB, labC, ext, C, n=256)
             res[prec] = {"ms": round(ms, 3), "effective_tflops": round(plan.info.flops / ms / 1e9, 3),
                          "max_componentwise_error_sampled": err,
-                         "digits": plan.info.split_slices if prec != "f64" else None}
+                         "digits": plan.info.split_slices if prec != "f64" else None,
+                         "bits": plan.info.split_bits if prec != "f64" else None}
             plan.close()
             torch.cuda.empty_cache()
         res["speedup_split_bf16_vs_f64"] = round(res["f64"]["ms"] / res["split_bf16"]["ms"], 3)
+        res["speedup_crt_int8_vs_f64"] = round(res["f64"]["ms"] / res["crt_int8"]["ms"], 3)
         out[name] = res
         print("[bench] precision workload %s: %s" % (name, res), file=sys.stderr, flush=True)
         del dA, dB, C

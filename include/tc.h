@@ -61,7 +61,10 @@ typedef enum {
 typedef enum {
   TC_PREC_F64 = 0,             /* FP64 MFMA / FP64 vector arithmetic throughout */
   TC_PREC_F64_SPLIT_BF16 = 1,  /* FP64 operands split into BF16 slices, BF16 MFMA, FP32 exact chunks, FP64 sum */
-  TC_PREC_F64_SPLIT_FP8 = 2    /* the same with FP8 E4M3 slices */
+  TC_PREC_F64_SPLIT_FP8 = 2,   /* the same with FP8 E4M3 slices */
+  TC_PREC_F64_CRT_INT8 = 3     /* FP64 operands rounded to integers of split_bits bits, multiplied exactly
+                                  as INT8 residues modulo split_slices coprime moduli (INT8 MFMA, INT32
+                                  accumulation), the product rebuilt by the Chinese remainder theorem */
 } tc_precision;
 
 /* Recipes of Sec. 3.2.  AUTO takes the class's recipe (3.2 -> GEMM, 3.1 ->
@@ -87,7 +90,8 @@ typedef struct {
   tc_precision precision;      /* default TC_PREC_F64 */
   tc_recipe recipe;            /* default TC_RECIPE_AUTO */
   tc_picker picker;            /* default TC_PICKER_RULES */
-  int split_slices;            /* slices per operand for split precision; 0 = default */
+  int split_slices;            /* slices per operand for split precision (moduli for TC_PREC_F64_CRT_INT8,
+                                  2 to 14); 0 = default (5 BF16, 8 FP8, 13 moduli) */
   int tile_id;                 /* GEMM tile configuration; -1 = chosen by the picker */
 } tc_options;
 
@@ -109,6 +113,8 @@ typedef struct {
                                   3 batched small slabs, 4 split-precision digits */
   int k_split;                 /* MFMA GEMM: segments of the contracted range (1 = none) */
   int picked_candidate;        /* candidate chosen by the MLP or the tune cache, -1: rules */
+  int split_bits;              /* split precision: bits each input keeps relative to its row's power-of-two
+                                  scale (every input is exact to 2^-split_bits of that scale), 0 otherwise */
 } tc_plan_info;
 
 /* Fills *opt with the defaults listed in tc_options. */

@@ -36,8 +36,8 @@ for _i, _n in enumerate(STATUS_NAMES):
     globals()[_n] = _i
 
 # tc_precision
-TC_PREC_F64, TC_PREC_F64_SPLIT_BF16, TC_PREC_F64_SPLIT_FP8 = 0, 1, 2
-PRECISIONS = {"f64": 0, "split_bf16": 1, "split_fp8": 2}
+TC_PREC_F64, TC_PREC_F64_SPLIT_BF16, TC_PREC_F64_SPLIT_FP8, TC_PREC_F64_CRT_INT8 = 0, 1, 2, 3
+PRECISIONS = {"f64": 0, "split_bf16": 1, "split_fp8": 2, "crt_int8": 3}
 # tc_recipe
 TC_RECIPE_AUTO, TC_RECIPE_GEMM, TC_RECIPE_COPY_GEMM, TC_RECIPE_GEMV, TC_RECIPE_GER, TC_RECIPE_DOT = range(6)
 RECIPES = {"auto": 0, "gemm": 1, "copy_gemm": 2, "gemv": 3, "ger": 4, "dot": 5}
@@ -64,7 +64,7 @@ class tc_plan_info(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t), ("precision", ctypes.c_int),
                 ("split_slices", ctypes.c_int), ("kernel", ctypes.c_int),
-                ("k_split", ctypes.c_int), ("picked_candidate", ctypes.c_int)]
+                ("k_split", ctypes.c_int), ("picked_candidate", ctypes.c_int), ("split_bits", ctypes.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -737,9 +737,14 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
     sp.b_kfast = an.b_kfast;
     sp.slices = an.slices;
     sp.fp8 = info.precision == TC_PREC_F64_SPLIT_FP8;
+    sp.crt = info.precision == TC_PREC_F64_CRT_INT8;
+    sp.bits = an.crt_bits;
+    sp.crt_tile = info.tile_id;
+    sp.c_nfast = an.crt_c_nfast;
     char* ws = (char*)workspace;
     sp.planesA = ws + an.planesA_off;
     sp.planesB = ws + an.planesB_off;
+    sp.zres = ws + an.zres_off;
     sp.sigA = (double*)(ws + an.sigA_off);
     sp.sigB = (double*)(ws + an.sigB_off);
     sp.part = (double*)(ws + an.part_off);

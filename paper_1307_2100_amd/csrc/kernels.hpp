@@ -150,10 +150,15 @@ struct SplitParams {
   Offs aM, aK, bN, bK, cM, cN;
   int64_t M, N, K, Mp, Np, Kp;
   bool a_rfast, a_kfast, b_rfast, b_kfast;
-  int slices;
+  int slices;    // digits per input, or moduli (crt)
   bool fp8;
+  bool crt;      // integer residues modulo `slices` coprime moduli
+  int bits;      // crt: inputs are rounded to integers of this many bits below the row scale
+  int crt_tile;  // crt: residue GEMM configuration (kCrtTiles)
+  bool c_nfast;  // crt: C's stride-1 mode is in the N group (rebuild lanes run along n)
   void* planesA;
   void* planesB;
+  void* zres;    // crt: residues of the product, slices * Mp * Np bytes
   double* sigA;
   double* sigB;
   double* part;  // max over both inputs of row_max_segments(R, K) * R doubles of scratch
@@ -178,6 +183,46 @@ inline constexpr SplitTile split_tile(bool fp8, int slices) {
   return fp8 ? SplitTile{32, 32, 128} : (slices <= 5 ? SplitTile{128, 64, 32} : SplitTile{64, 64, 32});
 }
 hipError_t launch_split_contraction(const SplitParams& sp, hipStream_t s);
+
+// Residue arithmetic (crt): pairwise coprime moduli, largest first.  Residues
+// lie in [-floor(p/2), ceil(p/2) - 1], so they fit in int8, and a product of
+// two is at most 2^14 in magnitude.
+constexpr int kCrtMaxModuli = 14;
+constexpr int kCrtDefaultModuli = 13;
+constexpr int kCrtModuli[kCrtMaxModuli] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199};
+// Tile configurations of the residue GEMM: (id, rows, columns, wavefronts
+// along rows, wavefronts along columns, k-steps of global loads in flight).
+// The contracted depth of a k-step is 64 (one INT8 matrix-core step).
+#define TC_CRT_TILES(X)        \
+  X(0, 128, 128, 2, 2, 1)      \
+  X(1, 128, 128, 2, 2, 2)      \
+  X(2, 256, 128, 4, 2, 2)      \
+  X(3, 128, 256, 2, 4, 2)      \
+  X(4, 256, 256, 2, 4, 2)      \
+  X(5, 256, 256, 4, 4, 2)       \
+  X(6, 256, 256, 4, 4, 1)
+struct CrtTileCfg {
+  int bm, bn, wgm, wgn, pf;
+};
+#define TC_CRT_ROW(id, bm, bn, wgm, wgn, pf) {bm, bn, wgm, wgn, pf},
+constexpr CrtTileCfg kCrtTiles[] = {TC_CRT_TILES(TC_CRT_ROW)};
+#undef TC_CRT_ROW
+constexpr int kCrtNumTiles = sizeof(kCrtTiles) / sizeof(kCrtTiles[0]);
+constexpr int kCrtDefaultTile = 6;
+constexpr int kCrtBK = 64;
+// Largest b <= 48 such that n moduli represent every sum of K products of
+// integers |a|, |b| <= 2^b without ambiguity: 2 K 4^b < P, P the product of
+// the moduli.  0 when no b >= 1 fits.  (Up to 2^48 the FP64 quotient y / p of
+// the residue pass rounds to the nearest integer exactly.)
+constexpr int kCrtMaxBits = 48;
+inline int crt_bits(int n, int64_t K) {
+  unsigned __int128 P = 1;
+  for (int i = 0; i < n; ++i) P *= (unsigned)kCrtModuli[i];
+  const unsigned __int128 k = (unsigned __int128)(K > 0 ? K : 1);
+  for (int b = kCrtMaxBits; b >= 1; --b)
+    if (k <= ((P - 1) >> (2 * b + 1))) return b;
+  return 0;
+}
 
 // Batch-dominated contractions: per-point slabs staged through LDS.
 struct SlabDesc {

@@ -298,7 +298,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
         }
     }
   }
-  if (opt.precision < TC_PREC_F64 || opt.precision > TC_PREC_F64_SPLIT_FP8 || opt.recipe < TC_RECIPE_AUTO ||
+  if (opt.precision < TC_PREC_F64 || opt.precision > TC_PREC_F64_CRT_INT8 || opt.recipe < TC_RECIPE_AUTO ||
       opt.recipe > TC_RECIPE_DOT || opt.tile_id < -1 || opt.tile_id >= kNumTiles || opt.split_slices < 0) {
     *err = "invalid tc_options field";
     return TC_ERR_INVALID_ARG;
@@ -337,6 +337,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
   info.tile_id = -1;
   info.k_split = 1;
   info.picked_candidate = -1;
+  info.split_bits = 0;
   info.unit_a = unit_mode(A0);
   info.unit_b = unit_mode(B0);
   info.unit_c = unit_mode(C0);
@@ -503,10 +504,13 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     // Split precision: every recipe runs as digit planes (gathered through the
     // strides once) multiplied on the BF16 / FP8 matrix cores.
     const bool fp8 = opt.precision == TC_PREC_F64_SPLIT_FP8;
-    const int maxs = fp8 ? kSplitMaxFp8 : kSplitMaxBf16;
-    int S = opt.split_slices > 0 ? opt.split_slices : (fp8 ? kSplitDefaultFp8 : kSplitDefaultBf16);
-    if (S > maxs) {
-      *err = fmt("split_slices %lld exceeds the maximum %lld for this digit type", S, maxs);
+    const bool crt = opt.precision == TC_PREC_F64_CRT_INT8;
+    const int maxs = crt ? kCrtMaxModuli : (fp8 ? kSplitMaxFp8 : kSplitMaxBf16);
+    int S = opt.split_slices > 0 ? opt.split_slices
+                                 : (crt ? kCrtDefaultModuli : (fp8 ? kSplitDefaultFp8 : kSplitDefaultBf16));
+    if (S > maxs || (crt && S < 2)) {
+      *err = fmt("split_slices %lld is outside the range %lld to ", S, crt ? 2 : 1) +
+             fmt("%lld for this digit type", maxs);
       return TC_ERR_INVALID_ARG;
     }
     if (info.L > 1) {
@@ -517,18 +521,37 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     an.kernel = Analysis::KERNEL_SPLIT;
     info.split_slices = S;
     an.slices = S;
-    const SplitTile t = split_tile(fp8, S);
+    if (crt) {
+      if (opt.tile_id >= kCrtNumTiles) {
+        *err = fmt("tile_id %lld is not a residue GEMM configuration (0 to %lld)", opt.tile_id, kCrtNumTiles - 1);
+        return TC_ERR_INVALID_ARG;
+      }
+      info.tile_id = opt.tile_id >= 0 ? opt.tile_id : kCrtDefaultTile;
+      an.crt_bits = crt_bits(S, info.K);
+      if (an.crt_bits < 1) {
+        *err = fmt("%lld moduli cannot hold sums of %lld products; use more moduli", S, info.K);
+        return TC_ERR_UNSUPPORTED;
+      }
+      info.split_bits = an.crt_bits;
+      an.crt_c_nfast = G[GN].n > 0 && G[GN].str[SC][0] == 1;
+    } else {
+      info.split_bits = fp8 ? 4 + 5 * (S - 1) : 8 + 9 * (S - 1);
+    }
+    const SplitTile t = crt ? SplitTile{kCrtTiles[info.tile_id].bm, kCrtTiles[info.tile_id].bn, kCrtBK}
+                            : split_tile(fp8, S);
     auto up = [](int64_t v, int64_t m) { return v <= 0 ? m : (v + m - 1) / m * m; };
     an.Mp = up(info.M, t.bm);
     an.Np = up(info.N, t.bn);
     an.Kp = up(info.K, fp8 ? 128 : t.bk);
-    const size_t esz = fp8 ? 1 : 2;
+    const size_t esz = fp8 || crt ? 1 : 2;
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     size_t off = 0;
     an.planesA_off = off;
     off = al(off + (size_t)S * an.Mp * an.Kp * esz);
     an.planesB_off = off;
     off = al(off + (size_t)S * an.Np * an.Kp * esz);
+    an.zres_off = off;
+    if (crt) off = al(off + (size_t)S * an.Mp * an.Np);
     an.sigA_off = off;
     off = al(off + (size_t)an.Mp * sizeof(double));
     an.sigB_off = off;

@@ -68,8 +68,10 @@ struct Analysis {
   bool b_nfast = false;     // kernel B's stride-1 mode leads its free group
   // split precision: padded sizes of the digit planes and workspace offsets
   int slices = 0;
+  int crt_bits = 0;         // residue form: bits of the integer inputs
+  bool crt_c_nfast = false; // residue form: C's stride-1 mode is in the N group
   int64_t Mp = 0, Np = 0, Kp = 0;
-  size_t planesA_off = 0, planesB_off = 0, sigA_off = 0, sigB_off = 0, part_off = 0;
+  size_t planesA_off = 0, planesB_off = 0, zres_off = 0, sigA_off = 0, sigB_off = 0, part_off = 0;
   int64_t elems[3] = {};    // entries of kernel A, kernel B, C (products of extents)
   // batched small contractions: slab descriptors (without pointers)
   int batched_P = 0;

@@ -24,6 +24,8 @@
 // The digits are written densely, k-contiguous and digit-interleaved per
 // k-step ([row][k-step][s][k]); gathering the tensor through its strides
 // happens once, in the split pass.
+#include <cmath>
+
 #include "kernels.hpp"
 
 namespace tc {
@@ -109,14 +111,11 @@ __device__ inline unsigned char e4m3_of_small_int(int v) {
 
 // Digits of a 64 x 64 tile of X staged in LDS; rows beyond R and columns
 // beyond K are written as zero digits.
-template <int S, bool FP8>
-__global__ __launch_bounds__(256) void split_planes_kernel(const double* __restrict__ X, Offs xr, Offs xk,
-                                                           int64_t R, int64_t K, int64_t Rp, int64_t Kp,
-                                                           const double* __restrict__ sigma, int rfast,
-                                                           void* __restrict__ planes) {
-  __shared__ double tile[64][65];
+// Stage the 64 x 64 tile of X at (r0, k0) in LDS, lanes along whichever of
+// r and k is stride-1 in memory (zeros beyond R and K).  256 threads.
+TC_DEV void gather_tile64(const double* __restrict__ X, const Offs& xr, const Offs& xk, int64_t R, int64_t K,
+                          int64_t r0, int64_t k0, int rfast, double (*tile)[65]) {
   const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.y * 64, k0 = (int64_t)blockIdx.x * 64;
   if (rfast) {
 #pragma unroll 4
     for (int i = 0; i < 16; ++i) {
@@ -132,6 +131,17 @@ __global__ __launch_bounds__(256) void split_planes_kernel(const double* __restr
       tile[rr][kk] = (r < R && k < K) ? X[off_at(xr, r) + off_at(xk, k)] : 0.0;
     }
   }
+}
+
+template <int S, bool FP8>
+__global__ __launch_bounds__(256) void split_planes_kernel(const double* __restrict__ X, Offs xr, Offs xk,
+                                                           int64_t R, int64_t K, int64_t Rp, int64_t Kp,
+                                                           const double* __restrict__ sigma, int rfast,
+                                                           void* __restrict__ planes) {
+  __shared__ double tile[64][65];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * 64, k0 = (int64_t)blockIdx.x * 64;
+  gather_tile64(X, xr, xk, R, K, r0, k0, rfast, tile);
   __syncthreads();
   constexpr double first = FP8 ? 16.0 : 256.0;   // 2^b
   constexpr double next = FP8 ? 32.0 : 512.0;    // 2^(b+1)
@@ -148,8 +158,15 @@ __global__ __launch_bounds__(256) void split_planes_kernel(const double* __restr
     if (r >= Rp || k >= Kp) continue;  // Kp is a multiple of KB, so all V entries are in range
     const double sg = sigma[r];
     double rem[V];
+    // exact: sg is a power of two, and so is its reciprocal unless sg is subnormal
+    if (sg >= 0x1p-1022) {
+      const double inv = 1.0 / sg;
 #pragma unroll
-    for (int v = 0; v < V; ++v) rem[v] = sg > 0.0 ? tile[rr][kk0 + v] / sg : 0.0;  // exact: sg is a power of two
+      for (int v = 0; v < V; ++v) rem[v] = tile[rr][kk0 + v] * inv;
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) rem[v] = sg > 0.0 ? tile[rr][kk0 + v] / sg : 0.0;
+    }
     const int64_t base = r * Kp * S + (k / KB) * (S * KB) + (k % KB);
 #pragma unroll
     for (int s_ = 0; s_ < S; ++s_) {
@@ -467,10 +484,297 @@ __global__ __launch_bounds__(64 * WGM * WGN) void split_gemm_fp8_kernel(SplitGem
   }
 }
 
-template <int S>
-hipError_t launch_planes(const double* X, Offs xr, Offs xk, int64_t R, int64_t K, int64_t Rp, int64_t Kp,
-                         double* sigma, double* part, bool rfast, bool kfast, bool fp8, void* planes,
-                         hipStream_t s) {
+// ---------------------------------------------------------------- residues
+// Moduli as FP64 for the residue pass (exact integers and rounded reciprocals).
+struct CrtModuli {
+  int n;
+  double p[kCrtMaxModuli];
+  double inv[kCrtMaxModuli];
+};
+
+// Integers y = rint(2^bits X[r,k] / sigma_r) (|y| <= 2^bits <= 2^48, exact in
+// FP64) of one 64 x 64 tile, written as residues modulo each p_i into the
+// int8 planes [i][Kp/64][Rp][64]: one k-step of 64 contracted indices of all
+// rows is contiguous, so the tile lands as one 4 KB block per modulus and a
+// k-step of a GEMM tile is one contiguous run of its rows.  Workgroup b
+// covers row block b % (Rp / 64) and k block b / (Rp / 64).
+//
+// For |y| <= 2^48 the product of y and the rounded reciprocal of p is within
+// 1/(16p) of y/p, closer than any half-integer is for odd p, so
+// q = rint(y / p) is the nearest integer and r = y - q p (one exact FMA) lies
+// in [-(p-1)/2, (p-1)/2].  For p = 256 the product is exact and r may be 128,
+// whose byte 0x80 reads back as -128: the same residue.
+__global__ __launch_bounds__(256) void crt_planes_kernel(const double* __restrict__ X, Offs xr, Offs xk, int64_t R,
+                                                         int64_t K, int64_t Rp, int64_t Kp,
+                                                         const double* __restrict__ sigma, int rfast, double lift,
+                                                         CrtModuli md, signed char* __restrict__ planes) {
+  __shared__ double tile[64][65];
+  const int tid = threadIdx.x;
+  const int64_t rblocks = Rp / 64;
+  const int64_t kb = (int64_t)blockIdx.x / rblocks;
+  const int64_t r0 = ((int64_t)blockIdx.x - kb * rblocks) * 64, k0 = kb * 64;
+  gather_tile64(X, xr, xk, R, K, r0, k0, rfast, tile);
+  __syncthreads();
+  // a thread takes 16 consecutive k of one row: one 16-byte store per modulus
+  const int rr = tid >> 2, kk0 = (tid & 3) * 16;
+  const int64_t r = r0 + rr;
+  const double sg = sigma[r];
+  double y[16];
+  // exact scaling by powers of two: one factor 2^bits / sg unless it would overflow
+  if (sg >= 0x1p-969) {
+    const double f = lift / sg;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) y[v] = rint(tile[rr][kk0 + v] * f);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) y[v] = sg > 0.0 ? rint(tile[rr][kk0 + v] / sg * lift) : 0.0;
+  }
+  signed char* dst = planes + k0 * Rp + r * 64 + kk0;  // k0 is a multiple of 64
+  const int64_t plane = Rp * Kp;
+  for (int i = 0; i < md.n; ++i) {
+    const double p = md.p[i], inv = md.inv[i];
+    u32x4 word = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const double q = rint(y[v] * inv);
+      const int rm = (int)fma(-q, p, y[v]);
+      word[v >> 2] |= ((unsigned)rm & 255u) << (8 * (v & 3));
+    }
+    *reinterpret_cast<u32x4*>(dst + i * plane) = word;
+  }
+}
+
+typedef int i4 __attribute__((ext_vector_type(4)));
+
+// Register stage of one k-step of the residue planes: each thread moves CPT
+// 16-byte chunks; chunk i of k-step ks sits at row[i] + ks * step[i] (the
+// k-step stride of its operand's planes).
+template <int CPT, int CHUNKS, int NT>
+struct KStager {
+  u32x4 v[CPT];
+  int dst[CPT];
+  __device__ inline void load(const signed char* const (&row)[CPT], const int64_t (&step)[CPT], int64_t ks,
+                              int tid) {
+#pragma unroll
+    for (int i = 0; i < CPT; ++i)
+      if (CHUNKS % NT == 0 || tid + i * NT < CHUNKS) v[i] = *(const u32x4*)(row[i] + ks * step[i]);
+  }
+  __device__ inline void store(signed char* st, int tid) const {
+#pragma unroll
+    for (int i = 0; i < CPT; ++i)
+      if (CHUNKS % NT == 0 || tid + i * NT < CHUNKS) *(u32x4*)(st + dst[i]) = v[i];
+  }
+};
+
+struct CrtGemmArgs {
+  const signed char* pa;   // residues of the kernel's A: [n][Kp/64][Mp][64]
+  const signed char* pb;   // residues of the kernel's B: [n][Kp/64][Np][64]
+  unsigned char* z;        // residues of the product in [0, p): [n][Np][Mp], or [n][Mp][Np] when zt
+  int64_t Mp, Np, Kp;
+  int n;
+  int zt;                  // 1: rows of z along m (n contiguous), to match an output stride-1 along n
+  int p[kCrtMaxModuli];
+};
+
+// One residue product per workgroup tile and modulus: Z_i = A_i B_i exactly in
+// INT32 (v_mfma_i32_16x16x64_i8), stored reduced modulo p_i.  Lane l supplies
+// 16 int8 of row l%16 of A and of column l%16 of B from the same 16
+// contracted positions (chunk l/16 of the 64), so any order the matrix core
+// gives those positions pairs A and B alike; accumulator element r holds
+// D[4(l/16) + r][l%16].  The tiles of all moduli are one sequence of row
+// blocks for the XCD-aware walk (modulus-major), so concurrent workgroups share
+// residue planes.  PF k-steps of global loads are in flight (register
+// stages) while the matrix cores work on the k-step staged in LDS.
+template <int BM, int BN, int WGM, int WGN, int PF>
+__global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_kernel(CrtGemmArgs g) {
+  static_assert(PF == 1 || PF == 2, "one or two k-steps in flight");
+  constexpr int BK = kCrtBK;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int CPR = BK / 16;  // 16-byte chunks per staged row
+  constexpr int CHUNKS = (BM + BN) * CPR;
+  constexpr int CPT = (CHUNKS + NT - 1) / NT;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  __shared__ __attribute__((aligned(16))) signed char sm[2][(BM + BN) * BK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int64_t tilesM = g.Mp / BM, tilesN = g.Np / BN;
+  int64_t tmx, tn;
+  xcd_tile(blockIdx.x, tilesM * g.n * tilesN, tilesM * g.n, tilesN, &tmx, &tn);
+  const int mod = (int)(tmx / tilesM);
+  const int64_t m0 = (tmx - (int64_t)mod * tilesM) * BM, n0 = tn * BN;
+  int p = g.p[0];
+#pragma unroll
+  for (int i = 1; i < kCrtMaxModuli; ++i) p = mod == i ? g.p[i] : p;  // no dynamic index into the arguments
+
+  const signed char* __restrict__ PA = g.pa + (int64_t)mod * g.Mp * g.Kp;
+  const signed char* __restrict__ PB = g.pb + (int64_t)mod * g.Np * g.Kp;
+  // chunk q of staged row r sits at slot q ^ ((r >> 2) & 3): the 16 rows of
+  // one fragment read fall in 16 distinct 16-byte bank groups
+  auto lds_off = [](int r, int q) { return r * BK + ((q ^ ((r >> 2) & 3)) << 4); };
+  KStager<CPT, CHUNKS, NT> stg[PF];
+  const signed char* srow[CPT];
+  int64_t kstep[CPT];
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int c = tid + i * NT;
+    const int row = (c < CHUNKS ? c : 0) / CPR, sub = (c < CHUNKS ? c : 0) % CPR;
+    srow[i] = (row < BM ? PA + (m0 + row) * BK : PB + (n0 + row - BM) * BK) + sub * 16;
+    kstep[i] = (row < BM ? g.Mp : g.Np) * BK;
+#pragma unroll
+    for (int f = 0; f < PF; ++f) stg[f].dst[i] = lds_off(row, sub);
+  }
+  i4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = i4{0, 0, 0, 0};
+
+  // every residue product is at most 2^14 in magnitude: reducing the sums
+  // modulo p every 2^16 contracted indices keeps them below 2^31
+  constexpr int64_t kReduce = 65536 / BK;
+  const int64_t ksteps = g.Kp / BK;
+  stg[0].load(srow, kstep, 0, tid);
+  if (PF == 2 && ksteps > 1) stg[PF - 1].load(srow, kstep, 1, tid);
+  stg[0].store(sm[0], tid);
+  __syncthreads();
+  const int fr = lane & 15, fq = lane >> 4;
+  for (int64_t ks = 0; ks < ksteps; ++ks) {
+    const int cur = ks & 1;
+    // register stage of k-step ks + PF: the set whose k-step was just staged
+    if (ks + PF < ksteps) {
+      if (PF == 1 || cur == 0)
+        stg[0].load(srow, kstep, ks + PF, tid);
+      else
+        stg[PF - 1].load(srow, kstep, ks + PF, tid);
+    }
+    const signed char* st = sm[cur];
+    i4 af[TM], bfr[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) af[i] = *(const i4*)(st + lds_off(wm * WM + i * 16 + fr, fq));
+#pragma unroll
+    for (int j = 0; j < TN; ++j) bfr[j] = *(const i4*)(st + lds_off(BM + wn * WN + j * 16 + fr, fq));
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    if ((ks + 1) % kReduce == 0) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] %= p;
+    }
+    // stage k-step ks + 1 from the register set that holds it
+    if (ks + 1 < ksteps) {
+      if (PF == 1 || cur == 1)
+        stg[0].store(sm[cur ^ 1], tid);
+      else
+        stg[PF - 1].store(sm[cur ^ 1], tid);
+    }
+    __syncthreads();
+  }
+  unsigned char* __restrict__ Z = g.z + (int64_t)mod * g.Mp * g.Np;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int64_t m = m0 + wm * WM + i * 16 + fq * 4;
+      const int64_t n = n0 + wn * WN + j * 16 + fr;
+      unsigned word = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int v = acc[i][j][r] % p;
+        v += v < 0 ? p : 0;
+        word |= (unsigned)v << (8 * r);
+      }
+      if (g.zt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Z[(m + r) * g.Np + n] = (unsigned char)(word >> (8 * r));
+      } else {
+        *reinterpret_cast<unsigned*>(Z + n * g.Mp + m) = word;
+      }
+    }
+}
+
+// Chinese-remainder rebuild: with M_i = P / p_i and w_i = M_i (M_i^-1 mod p_i)
+// (each below P), Z = sum_i z_i w_i mod P, taken in (-P/2, P/2].  P < 2^111,
+// so the sum of at most 14 terms below 2^8 P fits in 128 bits.
+struct CrtRebuild {
+  int n;
+  unsigned long long w[kCrtMaxModuli][2];  // (low, high) 64-bit words
+  unsigned long long P[2];
+  double inv_P;
+};
+
+// One thread takes four consecutive entries along the output's stride-1
+// group (m, or n when zt) at one index of the other (one 4-byte load per
+// modulus); C[m,n] = alpha sigma_m tau_n 2^(-2 bits) Z + beta C[m,n].
+__global__ __launch_bounds__(256) void crt_rebuild_kernel(const unsigned char* __restrict__ z, int64_t Mp, int64_t Np,
+                                                          int zt, const double* __restrict__ sa,
+                                                          const double* __restrict__ sb, double* __restrict__ C,
+                                                          Offs cM, Offs cN, int64_t M, int64_t N, double unit,
+                                                          double alpha, double beta, CrtRebuild cr) {
+  typedef unsigned __int128 u128;
+  typedef __int128 s128;
+  const u128 P = ((u128)cr.P[1] << 64) | cr.P[0];
+  // fast group: padded length (a multiple of 4) and true length; slow group: true length
+  const int64_t fp = zt ? Np : Mp, fl = zt ? N : M, sl = zt ? M : N;
+  const int64_t quads = fp / 4, units = quads * sl, plane = Mp * Np;
+  for (int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x; u < units; u += (int64_t)gridDim.x * 256) {
+    const int64_t so = u / quads, f4 = (u - so * quads) * 4;
+    if (f4 >= fl) continue;
+    // sum per 32-bit limb of the weights (each term below 2^40, 14 terms
+    // below 2^44), then one carry-propagating 128-bit sum per output
+    unsigned long long limb[4][4] = {};
+    for (int i = 0; i < cr.n; ++i) {
+      const unsigned word = *reinterpret_cast<const unsigned*>(z + i * plane + so * fp + f4);
+      const unsigned w0 = (unsigned)cr.w[i][0], w1 = (unsigned)(cr.w[i][0] >> 32);
+      const unsigned w2 = (unsigned)cr.w[i][1], w3 = (unsigned)(cr.w[i][1] >> 32);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const unsigned long long zr = (word >> (8 * r)) & 255u;
+        limb[r][0] += zr * w0;
+        limb[r][1] += zr * w1;
+        limb[r][2] += zr * w2;
+        limb[r][3] += zr * w3;
+      }
+    }
+    u128 S[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      S[r] = (u128)limb[r][0] + ((u128)limb[r][1] << 32) + ((u128)limb[r][2] << 64) + ((u128)limb[r][3] << 96);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (f4 + r >= fl) break;
+      const int64_t m = zt ? so : f4 + r, n = zt ? f4 + r : so;
+      // quotient from FP64 (S / P < 2^12, so the estimate is at most one off)
+      const double sd = (double)(unsigned long long)(S[r] >> 64) * 0x1p64 + (double)(unsigned long long)S[r];
+      const unsigned long long q = (unsigned long long)floor(sd * cr.inv_P);
+      s128 R = (s128)(S[r] - (u128)q * P);
+      if (R < 0)
+        R += (s128)P;
+      else if (R >= (s128)P)
+        R -= (s128)P;
+      if (2 * R > (s128)P) R -= (s128)P;
+      const bool neg = R < 0;
+      const u128 U = neg ? (u128)(-R) : (u128)R;
+      double v = (double)(unsigned long long)(U >> 64) * 0x1p64 + (double)(unsigned long long)U;
+      v = neg ? -v : v;
+      double* dst = C + off_at(cM, m) + off_at(cN, n);
+      double out = alpha * (sa[m] * (sb[n] * unit) * v);
+      if (beta != 0.0) out += beta * *dst;
+      *dst = out;
+    }
+  }
+}
+
+// Row scales of one input: one wavefront per row when k is stride-1 (and
+// rows are not), else per-segment maxima and a fixed-order second pass.
+hipError_t launch_row_scales(const double* X, Offs xr, Offs xk, int64_t R, int64_t K, int64_t Rp, double* sigma,
+                             double* part, bool rfast, bool kfast, hipStream_t s) {
   if (kfast && !rfast) {
     hipLaunchKernelGGL(row_scale_wave_kernel, dim3((unsigned)((Rp + 3) / 4)), dim3(256), 0, s, X, xr, xk, R, K, Rp,
                        sigma);
@@ -483,7 +787,111 @@ hipError_t launch_planes(const double* X, Offs xr, Offs xk, int64_t R, int64_t K
     hipLaunchKernelGGL(row_scale_from_parts_kernel, dim3((unsigned)((Rp + 255) / 256)), dim3(256), 0, s, part, R,
                        nseg, Rp, sigma);
   }
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_crt(const SplitParams& sp, hipStream_t s) {
+  const int n = sp.slices;
+  if (n < 2 || n > kCrtMaxModuli || sp.bits < 1 || sp.bits > kCrtMaxBits) return hipErrorInvalidValue;
+  if (sp.crt_tile < 0 || sp.crt_tile >= kCrtNumTiles) return hipErrorInvalidValue;
+  const CrtTileCfg t = kCrtTiles[sp.crt_tile];
+  if (sp.Mp % t.bm || sp.Np % t.bn || sp.Kp % kCrtBK) return hipErrorInvalidValue;
+  CrtModuli md{};
+  md.n = n;
+  for (int i = 0; i < n; ++i) {
+    md.p[i] = kCrtModuli[i];
+    md.inv[i] = 1.0 / kCrtModuli[i];
+  }
+  const double lift = std::ldexp(1.0, sp.bits);
+  constexpr int64_t kMaxBlocks = 0xffffffffLL / 256;
+  hipError_t e;
+  for (int op = 0; op < 2; ++op) {
+    const double* X = op ? sp.B : sp.A;
+    const Offs xr = op ? sp.bN : sp.aM, xk = op ? sp.bK : sp.aK;
+    const int64_t R = op ? sp.N : sp.M, Rp = op ? sp.Np : sp.Mp;
+    double* sig = op ? sp.sigB : sp.sigA;
+    e = launch_row_scales(X, xr, xk, R, sp.K, Rp, sig, sp.part, op ? sp.b_rfast : sp.a_rfast,
+                          op ? sp.b_kfast : sp.a_kfast, s);
+    if (e != hipSuccess) return e;
+    const int64_t blocks = (Rp / 64) * (sp.Kp / 64);
+    if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(crt_planes_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, xr, xk, R, sp.K, Rp, sp.Kp, sig,
+                       (op ? sp.b_rfast : sp.a_rfast) ? 1 : 0, lift, md,
+                       (signed char*)(op ? sp.planesB : sp.planesA));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  CrtGemmArgs g{};
+  g.pa = (const signed char*)sp.planesA;
+  g.pb = (const signed char*)sp.planesB;
+  g.z = (unsigned char*)sp.zres;
+  g.Mp = sp.Mp;
+  g.Np = sp.Np;
+  g.Kp = sp.Kp;
+  g.n = n;
+  g.zt = sp.c_nfast ? 1 : 0;
+  for (int i = 0; i < kCrtMaxModuli; ++i) g.p[i] = kCrtModuli[i];
+  const int64_t gblocks = (sp.Mp / t.bm) * (sp.Np / t.bn) * n;
+  if (gblocks > kMaxBlocks) return hipErrorInvalidConfiguration;
+  switch (sp.crt_tile) {
+#define TC_CRT_LAUNCH(id, bm, bn, wgm, wgn, pf)                                                         \
+  case id:                                                                                            \
+    hipLaunchKernelGGL((crt_gemm_kernel<bm, bn, wgm, wgn, pf>), dim3((unsigned)gblocks), dim3(64 * wgm * wgn), 0, s, g); \
+    break;
+    TC_CRT_TILES(TC_CRT_LAUNCH)
+#undef TC_CRT_LAUNCH
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // weights: M_i as the product of the other moduli (no 128-bit division)
+  typedef unsigned __int128 u128;
+  CrtRebuild cr{};
+  cr.n = n;
+  u128 P = 1;
+  double Pd = 1.0;
+  for (int i = 0; i < n; ++i) {
+    P *= (unsigned)kCrtModuli[i];
+    Pd *= kCrtModuli[i];
+  }
+  for (int i = 0; i < n; ++i) {
+    const unsigned pi = (unsigned)kCrtModuli[i];
+    u128 Mi = 1;
+    unsigned mi = 1;  // M_i mod p_i
+    for (int j = 0; j < n; ++j)
+      if (j != i) {
+        Mi *= (unsigned)kCrtModuli[j];
+        mi = (unsigned)((unsigned long long)mi * (unsigned)kCrtModuli[j] % pi);
+      }
+    unsigned inv = 0;
+    for (unsigned x = 1; x < pi; ++x)
+      if ((unsigned long long)mi * x % pi == 1) {
+        inv = x;
+        break;
+      }
+    if (inv == 0) return hipErrorInvalidValue;  // moduli not coprime
+    const u128 w = Mi * inv;
+    cr.w[i][0] = (unsigned long long)w;
+    cr.w[i][1] = (unsigned long long)(w >> 64);
+  }
+  cr.P[0] = (unsigned long long)P;
+  cr.P[1] = (unsigned long long)(P >> 64);
+  cr.inv_P = 1.0 / Pd;
+  const int64_t units = sp.c_nfast ? (sp.Np / 4) * sp.M : (sp.Mp / 4) * sp.N;
+  if (units > 0) {
+    const int64_t want = (units + 255) / 256;
+    const unsigned blocks = (unsigned)(want < kMaxGridBlocks ? want : kMaxGridBlocks);
+    hipLaunchKernelGGL(crt_rebuild_kernel, dim3(blocks), dim3(256), 0, s, (const unsigned char*)sp.zres, sp.Mp, sp.Np,
+                       sp.c_nfast ? 1 : 0, sp.sigA, sp.sigB, sp.C, sp.cM, sp.cN, sp.M, sp.N, std::ldexp(1.0, -2 * sp.bits), sp.alpha,
+                       sp.beta, cr);
+  }
+  return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_planes(const double* X, Offs xr, Offs xk, int64_t R, int64_t K, int64_t Rp, int64_t Kp,
+                         double* sigma, double* part, bool rfast, bool kfast, bool fp8, void* planes,
+                         hipStream_t s) {
+  hipError_t e = launch_row_scales(X, xr, xk, R, K, Rp, sigma, part, rfast, kfast, s);
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)((Kp + 63) / 64), (unsigned)((Rp + 63) / 64));
   if (fp8)
@@ -517,6 +925,7 @@ hipError_t launch_split_gemm(const SplitGemmArgs& a, bool fp8, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_split_contraction(const SplitParams& sp, hipStream_t s) {
+  if (sp.crt) return launch_crt(sp, s);
   const int S = sp.slices;
   const bool fp8 = sp.fp8;
   hipError_t e = hipSuccess;

@@ -239,6 +239,53 @@ def test_split_precision_plans_have_no_copy_step():
     assert info.split_slices == 8
 
 
+CRT_MODULI = [256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199]
+
+
+def test_crt_moduli_are_pairwise_coprime_and_fit_int8():
+    """Residues in [-floor(p/2), ceil(p/2) - 1] must fit in int8 and the
+    moduli must be pairwise coprime for the Chinese remainder theorem."""
+    import math
+    for i, p in enumerate(CRT_MODULI):
+        assert -(p // 2) >= -128 and (p + 1) // 2 - 1 <= 127
+        for q in CRT_MODULI[i + 1:]:
+            assert math.gcd(p, q) == 1, (p, q)
+
+
+def test_crt_plan_bits_and_limits():
+    """The residue form keeps b bits per input, the largest b <= 48 with
+    2 K 4^b < P (P the product of the moduli used), so that every sum of K
+    products of integers |a|, |b| <= 2^b is recovered without ambiguity."""
+    def expected_bits(n, K):
+        P = 1
+        for p in CRT_MODULI[:n]:
+            P *= p
+        return max([b for b in range(1, 49) if 2 * K * 4 ** b < P] or [0])
+
+    ext = {"i": 40, "k": 300, "j": 7}
+    info = analyze("ik", "kj", "ij", ext, precision="crt_int8")
+    assert info.split_slices == 13 and info.split_bits == expected_bits(13, 300)
+    assert info.kernel == 4 and info.workspace_bytes > 0 and info.precision == tc.TC_PREC_F64_CRT_INT8
+    for n in range(2, 15):
+        for K in (1, 4, 300, 4096, 36864, 70000):
+            e = {"i": 3, "k": K, "j": 2}
+            b = expected_bits(n, K)
+            if b == 0:
+                with pytest.raises(tc.TCError) as err:
+                    analyze("ik", "kj", "ij", e, precision="crt_int8", split_slices=n)
+                assert err.value.status == tc.TC_ERR_UNSUPPORTED
+            else:
+                assert analyze("ik", "kj", "ij", e, precision="crt_int8", split_slices=n).split_bits == b
+    for n in (1, 15):
+        with pytest.raises(tc.TCError) as err:
+            analyze("ik", "kj", "ij", ext, precision="crt_int8", split_slices=n)
+        assert err.value.status == tc.TC_ERR_INVALID_ARG
+    # the digit forms report their bits too: 8 + 9 (S - 1) for BF16, 4 + 5 (S - 1) for FP8
+    assert analyze("ik", "kj", "ij", ext, precision="split_bf16").split_bits == 44
+    assert analyze("ik", "kj", "ij", ext, precision="split_fp8").split_bits == 39
+    assert analyze("ik", "kj", "ij", ext).split_bits == 0
+
+
 def test_fast_division_method():
     """The slab engine divides by plan-time constants with a multiply and a
     shift (mul = ceil(2^p / d), p = 31 + ceil(log2 d)); check the method

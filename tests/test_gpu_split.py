@@ -1,10 +1,13 @@
-"""Split-precision contractions (FP64 digits on BF16 / FP8 matrix cores)
-against the compensated FP64 oracle.
+"""Split-precision contractions (FP64 digits on BF16 / FP8 matrix cores, and
+FP64 inputs as integers multiplied through INT8 residues) against the
+compensated FP64 oracle.
 
-Integer-valued inputs in [-4, 4] fit in one digit, so every product and sum
-is exact and the result must equal the oracle bit for bit.  Otherwise the
-componentwise error must stay within the bound of the digit count: BF16 with
-the default 5 digits (8 + 4x9 = 44 bits per input) is held to 1e-10, also on
+Integer-valued inputs in [-4, 4] fit in one digit, and in the integer form
+of the residue path, so every product and sum is exact and the result must
+equal the oracle bit for bit.  Otherwise the componentwise error must stay
+within the bound of the bits kept per input: BF16 with the default 5 digits
+(8 + 4x9 = 44 bits) and the residue form with the default 13 moduli (42 to
+52 bits, depending on the contracted extent) are held to 1e-10, also on
 inputs whose slices are scaled by 10^U(-3,3)."""
 import numpy as np
 import pytest
@@ -46,7 +49,7 @@ def _run(labA, labB, labC, A, B, precision, slices=0, alpha=1.0, beta=0.0, C0=No
     return C.cpu().numpy(), info
 
 
-@pytest.mark.parametrize("precision", ["split_bf16", "split_fp8"])
+@pytest.mark.parametrize("precision", ["split_bf16", "split_fp8", "crt_int8"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_split_exact_on_integers(case, precision):
     name, labA, labB, labC, ext = case
@@ -65,6 +68,75 @@ def test_split_bf16_default_meets_1e10(case, kind):
     ref, absr = reference(A, labA, B, labB, labC)
     err = componentwise_error(got, ref, absr)
     print(name, kind, "bf16 S=%d componentwise error %.3e" % (info["split_slices"], err))
+    assert err <= SPLIT_TOL
+
+
+@pytest.mark.parametrize("kind", ["uniform", "scaled_normal"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_crt_default_meets_1e10(case, kind):
+    name, labA, labB, labC, ext = case
+    A, B = synth.make_operands(25, labA, labB, ext, kind=kind)
+    got, info = _run(labA, labB, labC, A, B, "crt_int8")
+    ref, absr = reference(A, labA, B, labB, labC)
+    err = componentwise_error(got, ref, absr)
+    print(name, kind, "crt %d moduli, %d bits: componentwise error %.3e" % (info["split_slices"], info["split_bits"], err))
+    assert info["split_slices"] == 13 and info["split_bits"] >= 42
+    assert err <= SPLIT_TOL
+
+
+def test_crt_error_falls_with_moduli():
+    """Rounding each input to b bits below its row scale errs by at most
+    2^-(b+1) of that scale per entry; more moduli buy more bits (about 4 per
+    modulus) until FP64 rounding of the result dominates."""
+    name, labA, labB, labC, ext = CASES[1]
+    A, B = synth.make_operands(26, labA, labB, ext, kind="scaled_normal")
+    ref, absr = reference(A, labA, B, labB, labC)
+    errs, bits = [], []
+    for n in range(2, 15):
+        got, info = _run(labA, labB, labC, A, B, "crt_int8", slices=n)
+        errs.append(componentwise_error(got, ref, absr))
+        bits.append(info["split_bits"])
+    print("crt", list(zip(bits, ["%.2e" % e for e in errs])))
+    for b, e in zip(bits, errs):
+        assert e <= max(2.0 ** (6 - b), 1e-14), (b, e)
+    for (b0, e0), (b1, e1) in zip(zip(bits, errs), zip(bits[1:], errs[1:])):
+        assert b1 >= b0 + 3 or b1 == 48
+        assert e1 <= max(e0 * 0.25, 1e-13)
+
+
+def test_crt_residues_exact_at_48_bits():
+    """Inputs m 2^-40 with |m| < 2^47: with 14 moduli and a short contraction
+    every input becomes an integer of up to 48 bits exactly, so the residue
+    products and the Chinese-remainder rebuild are exact and only the final
+    conversion to FP64 rounds (about one ulp of the result).  A residue pass
+    whose quotient y / p were misrounded at that size would fail this."""
+    labA, labB, labC = "ik", "kj", "ij"
+    ext = {"i": 70, "k": 100, "j": 45}
+    g = np.random.default_rng(29)
+    lim = 2 ** 47 - 1
+    A = np.asfortranarray(g.integers(-lim, lim, size=(70, 100)).astype(np.float64) * 2.0 ** -40)
+    B = np.asfortranarray(g.integers(-lim, lim, size=(100, 45)).astype(np.float64) * 2.0 ** -40)
+    got, info = _run(labA, labB, labC, A, B, "crt_int8", slices=14)
+    assert info["split_bits"] == 48
+    ref, absr = reference(A, labA, B, labB, labC)
+    err = componentwise_error(got, ref, absr)
+    print("crt 48-bit inputs: componentwise error %.3e" % err)
+    assert err <= 1e-15
+
+
+def test_crt_long_contraction_reduces_partial_sums():
+    """More than 2^16 contracted indices: the residue sums are reduced modulo
+    p on the way (exact on integers, within the bound on real inputs)."""
+    labA, labB, labC = "ik", "k", "i"
+    ext = {"i": 131, "k": 70001}
+    A, B = synth.make_operands(27, labA, labB, ext, kind="integers")
+    got, info = _run(labA, labB, labC, A, B, "crt_int8")
+    assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
+    A, B = synth.make_operands(28, labA, labB, ext, kind="uniform")
+    got, info = _run(labA, labB, labC, A, B, "crt_int8")
+    ref, absr = reference(A, labA, B, labB, labC)
+    err = componentwise_error(got, ref, absr)
+    print("crt K=70001 %d bits: componentwise error %.3e" % (info["split_bits"], err))
     assert err <= SPLIT_TOL
 
 
@@ -87,7 +159,7 @@ def test_split_alpha_beta():
     name, labA, labB, labC, ext = CASES[0]
     A, B = synth.make_operands(24, labA, labB, ext, kind="integers")
     C0 = synth.integers([ext[l] for l in labC], 5)
-    for precision in ("split_bf16", "split_fp8"):
+    for precision in ("split_bf16", "split_fp8", "crt_int8"):
         got, _ = _run(labA, labB, labC, A, B, precision, alpha=-2.0, beta=0.5, C0=C0)
         assert np.array_equal(got, -2.0 * oracle.contract(A, labA, B, labB, labC) + 0.5 * C0)
 
