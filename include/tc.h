@@ -67,6 +67,9 @@ typedef enum {
                                   accumulation), the product rebuilt by the Chinese remainder theorem */
 } tc_precision;
 
+/* Residue GEMM configurations of TC_PREC_F64_CRT_INT8 plans (tc_options.tile_id). */
+#define TC_CRT_NUM_TILES 10
+
 /* Recipes of Sec. 3.2.  AUTO takes the class's recipe (3.2 -> GEMM, 3.1 ->
  * COPY_GEMM, 2 -> GEMV, 1 -> DOT, no contracted index -> GER); any other
  * value forces that recipe, which every class can run (results agree to
@@ -92,7 +95,9 @@ typedef struct {
   tc_picker picker;            /* default TC_PICKER_RULES */
   int split_slices;            /* slices per operand for split precision (moduli for TC_PREC_F64_CRT_INT8,
                                   2 to 14); 0 = default (5 BF16, 8 FP8, 13 moduli) */
-  int tile_id;                 /* GEMM tile configuration; -1 = chosen by the picker */
+  int tile_id;                 /* GEMM tile configuration; -1 = chosen by the picker.  For
+                                  TC_PREC_F64_CRT_INT8 plans: residue GEMM configuration, 0 to
+                                  TC_CRT_NUM_TILES - 1, -1 = the default */
 } tc_options;
 
 typedef struct {

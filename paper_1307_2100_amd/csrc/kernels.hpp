@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "../../include/tc.h"
+
 // Grid-stride kernels launch at most this many workgroups (a grid's total
 // thread count must stay below 2^32).
 constexpr int64_t kMaxGridBlocks = 1 << 20;
@@ -166,7 +168,7 @@ struct SplitParams {
 };
 // Contracted segments of the row-maximum pass when rows are stride-1.
 inline int64_t row_max_segments(int64_t R, int64_t K) {
-  int64_t seg = R > 0 ? (262144 + R - 1) / R : 1;
+  int64_t seg = R > 0 ? (1048576 + R - 1) / R : 1;
   const int64_t cap = K / 64 > 1 ? K / 64 : 1;
   return seg < 1 ? 1 : (seg > cap ? cap : seg);
 }
@@ -191,8 +193,10 @@ constexpr int kCrtMaxModuli = 14;
 constexpr int kCrtDefaultModuli = 13;
 constexpr int kCrtModuli[kCrtMaxModuli] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199};
 // Tile configurations of the residue GEMM: (id, rows, columns, wavefronts
-// along rows, wavefronts along columns, k-steps of global loads in flight).
-// The contracted depth of a k-step is 64 (one INT8 matrix-core step).
+// along rows, wavefronts along columns, pipeline depth).  Depth 1 or 2: k-steps
+// of global loads in flight through registers; 3 or more: stages of an LDS
+// ring filled by direct global-to-LDS copies.  The contracted depth of a
+// k-step is 64 (one INT8 matrix-core step).
 #define TC_CRT_TILES(X)        \
   X(0, 128, 128, 2, 2, 1)      \
   X(1, 128, 128, 2, 2, 2)      \
@@ -200,7 +204,10 @@ constexpr int kCrtModuli[kCrtMaxModuli] = {256, 255, 253, 251, 247, 241, 239, 23
   X(3, 128, 256, 2, 4, 2)      \
   X(4, 256, 256, 2, 4, 2)      \
   X(5, 256, 256, 4, 4, 2)       \
-  X(6, 256, 256, 4, 4, 1)
+  X(6, 256, 256, 4, 4, 1)       \
+  X(7, 256, 256, 4, 4, 3)       \
+  X(8, 256, 256, 4, 4, 4)       \
+  X(9, 256, 128, 4, 2, 4)
 struct CrtTileCfg {
   int bm, bn, wgm, wgn, pf;
 };
@@ -208,7 +215,8 @@ struct CrtTileCfg {
 constexpr CrtTileCfg kCrtTiles[] = {TC_CRT_TILES(TC_CRT_ROW)};
 #undef TC_CRT_ROW
 constexpr int kCrtNumTiles = sizeof(kCrtTiles) / sizeof(kCrtTiles[0]);
-constexpr int kCrtDefaultTile = 6;
+static_assert(kCrtNumTiles == TC_CRT_NUM_TILES, "tile table and header agree");
+constexpr int kCrtDefaultTile = 8;
 constexpr int kCrtBK = 64;
 // Largest b <= 48 such that n moduli represent every sum of K products of
 // integers |a|, |b| <= 2^b without ambiguity: 2 K 4^b < P, P the product of

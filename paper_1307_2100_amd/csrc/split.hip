@@ -58,9 +58,15 @@ __global__ __launch_bounds__(256) void row_max_rows_kernel(const double* __restr
   if (r >= R) return;
   const double* row = X + off_at(xr, r);
   const int64_t k0 = sgi * seg_len, k1 = k0 + seg_len < K ? k0 + seg_len : K;
-  double mx = 0.0;
-  for (int64_t k = k0; k < k1; ++k) mx = fmax(mx, fabs(row[off_at(xk, k)]));
-  part[sgi * R + r] = mx;
+  // four independent maxima so that four loads are in flight per thread
+  double m4[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t k = k0;
+  for (; k + 4 <= k1; k += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) m4[u] = fmax(m4[u], fabs(row[off_at(xk, k + u)]));
+  }
+  for (; k < k1; ++k) m4[0] = fmax(m4[0], fabs(row[off_at(xk, k)]));
+  part[sgi * R + r] = fmax(fmax(m4[0], m4[1]), fmax(m4[2], m4[3]));
 }
 
 __global__ __launch_bounds__(256) void row_scale_from_parts_kernel(const double* __restrict__ part, int64_t R,
@@ -547,17 +553,19 @@ __global__ __launch_bounds__(256) void crt_planes_kernel(const double* __restric
 typedef int i4 __attribute__((ext_vector_type(4)));
 
 // Register stage of one k-step of the residue planes: each thread moves CPT
-// 16-byte chunks; chunk i of k-step ks sits at row[i] + ks * step[i] (the
-// k-step stride of its operand's planes).
-template <int CPT, int CHUNKS, int NT>
+// 16-byte chunks.  The first ACH chunks of the tile belong to A; with ACH a
+// multiple of NT, chunk i of every thread comes from the same operand, so the
+// k-step base of each operand is one uniform pointer and a chunk needs only
+// its 32-bit offset.
+template <int CPT, int CHUNKS, int NT, int ACH>
 struct KStager {
+  static_assert(ACH % NT == 0, "each chunk slot from one operand");
   u32x4 v[CPT];
   int dst[CPT];
-  __device__ inline void load(const signed char* const (&row)[CPT], const int64_t (&step)[CPT], int64_t ks,
-                              int tid) {
+  __device__ inline void load(const signed char* a, const signed char* b, const int (&off)[CPT], int tid) {
 #pragma unroll
     for (int i = 0; i < CPT; ++i)
-      if (CHUNKS % NT == 0 || tid + i * NT < CHUNKS) v[i] = *(const u32x4*)(row[i] + ks * step[i]);
+      if (CHUNKS % NT == 0 || tid + i * NT < CHUNKS) v[i] = *(const u32x4*)((i * NT < ACH ? a : b) + off[i]);
   }
   __device__ inline void store(signed char* st, int tid) const {
 #pragma unroll
@@ -575,6 +583,49 @@ struct CrtGemmArgs {
   int zt;                  // 1: rows of z along m (n contiguous), to match an output stride-1 along n
   int p[kCrtMaxModuli];
 };
+
+// Product residues z = Z mod p in [0, p) of one wavefront's TM x TN
+// fragments (rows from mw, columns from nw), one byte per output.
+template <int TM, int TN, int WM, int WN>
+TC_DEV void crt_store_residues(const CrtGemmArgs& g, const i4 (&acc)[TM][TN], int mod, int p, int64_t mw, int64_t nw,
+                               int lane) {
+  const int fr = lane & 15, fq = lane >> 4;
+  unsigned char* __restrict__ Z = g.z + (int64_t)mod * g.Mp * g.Np;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int64_t m = mw + i * 16 + fq * 4;
+      const int64_t n = nw + j * 16 + fr;
+      unsigned word = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int v = acc[i][j][r] % p;
+        v += v < 0 ? p : 0;
+        word |= (unsigned)v << (8 * r);
+      }
+      if (g.zt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Z[(m + r) * g.Np + n] = (unsigned char)(word >> (8 * r));
+      } else {
+        *reinterpret_cast<unsigned*>(Z + n * g.Mp + m) = word;
+      }
+    }
+}
+
+// Tile of the residue GEMM for workgroup bid: modulus, first row, first column.
+TC_DEV void crt_tile_of(const CrtGemmArgs& g, int BM, int BN, int* mod, int* p, int64_t* m0, int64_t* n0) {
+  const int64_t tilesM = g.Mp / BM, tilesN = g.Np / BN;
+  int64_t tmx, tn;
+  xcd_tile(blockIdx.x, tilesM * g.n * tilesN, tilesM * g.n, tilesN, &tmx, &tn);
+  *mod = (int)(tmx / tilesM);
+  *m0 = (tmx - (int64_t)*mod * tilesM) * BM;
+  *n0 = tn * BN;
+  int q = g.p[0];
+#pragma unroll
+  for (int i = 1; i < kCrtMaxModuli; ++i) q = *mod == i ? g.p[i] : q;  // no dynamic index into the arguments
+  *p = q;
+}
 
 // One residue product per workgroup tile and modulus: Z_i = A_i B_i exactly in
 // INT32 (v_mfma_i32_16x16x64_i8), stored reduced modulo p_i.  Lane l supplies
@@ -599,32 +650,32 @@ __global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_kernel(CrtGemmArgs g)
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
-  const int64_t tilesM = g.Mp / BM, tilesN = g.Np / BN;
-  int64_t tmx, tn;
-  xcd_tile(blockIdx.x, tilesM * g.n * tilesN, tilesM * g.n, tilesN, &tmx, &tn);
-  const int mod = (int)(tmx / tilesM);
-  const int64_t m0 = (tmx - (int64_t)mod * tilesM) * BM, n0 = tn * BN;
-  int p = g.p[0];
-#pragma unroll
-  for (int i = 1; i < kCrtMaxModuli; ++i) p = mod == i ? g.p[i] : p;  // no dynamic index into the arguments
+  int mod, p;
+  int64_t m0, n0;
+  crt_tile_of(g, BM, BN, &mod, &p, &m0, &n0);
 
   const signed char* __restrict__ PA = g.pa + (int64_t)mod * g.Mp * g.Kp;
   const signed char* __restrict__ PB = g.pb + (int64_t)mod * g.Np * g.Kp;
   // chunk q of staged row r sits at slot q ^ ((r >> 2) & 3): the 16 rows of
   // one fragment read fall in 16 distinct 16-byte bank groups
   auto lds_off = [](int r, int q) { return r * BK + ((q ^ ((r >> 2) & 3)) << 4); };
-  KStager<CPT, CHUNKS, NT> stg[PF];
-  const signed char* srow[CPT];
-  int64_t kstep[CPT];
+  KStager<CPT, CHUNKS, NT, BM * CPR> stg[PF];
+  int soff[CPT];
 #pragma unroll
   for (int i = 0; i < CPT; ++i) {
     const int c = tid + i * NT;
     const int row = (c < CHUNKS ? c : 0) / CPR, sub = (c < CHUNKS ? c : 0) % CPR;
-    srow[i] = (row < BM ? PA + (m0 + row) * BK : PB + (n0 + row - BM) * BK) + sub * 16;
-    kstep[i] = (row < BM ? g.Mp : g.Np) * BK;
+    soff[i] = (row < BM ? row : row - BM) * BK + sub * 16;
 #pragma unroll
     for (int f = 0; f < PF; ++f) stg[f].dst[i] = lds_off(row, sub);
   }
+  // k-step ks of this tile's rows: one contiguous run per operand
+  const signed char* const PA0 = PA + m0 * BK;
+  const signed char* const PB0 = PB + n0 * BK;
+  const int64_t kstepA = g.Mp * BK, kstepB = g.Np * BK;
+  auto load = [&](KStager<CPT, CHUNKS, NT, BM * CPR>& st, int64_t ks) {
+    st.load(PA0 + ks * kstepA, PB0 + ks * kstepB, soff, tid);
+  };
   i4 acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -634,22 +685,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_kernel(CrtGemmArgs g)
   // every residue product is at most 2^14 in magnitude: reducing the sums
   // modulo p every 2^16 contracted indices keeps them below 2^31
   constexpr int64_t kReduce = 65536 / BK;
-  const int64_t ksteps = g.Kp / BK;
-  stg[0].load(srow, kstep, 0, tid);
-  if (PF == 2 && ksteps > 1) stg[PF - 1].load(srow, kstep, 1, tid);
-  stg[0].store(sm[0], tid);
-  __syncthreads();
+  const int64_t ksteps = g.Kp / BK, last = ksteps - 1;
   const int fr = lane & 15, fq = lane >> 4;
-  for (int64_t ks = 0; ks < ksteps; ++ks) {
-    const int cur = ks & 1;
-    // register stage of k-step ks + PF: the set whose k-step was just staged
-    if (ks + PF < ksteps) {
-      if (PF == 1 || cur == 0)
-        stg[0].load(srow, kstep, ks + PF, tid);
-      else
-        stg[PF - 1].load(srow, kstep, ks + PF, tid);
-    }
-    const signed char* st = sm[cur];
+  auto compute = [&](const signed char* st, int64_t ks) {
     i4 af[TM], bfr[TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i) af[i] = *(const i4*)(st + lds_off(wm * WM + i * 16 + fr, fq));
@@ -667,36 +705,136 @@ __global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_kernel(CrtGemmArgs g)
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc[i][j][r] %= p;
     }
-    // stage k-step ks + 1 from the register set that holds it
-    if (ks + 1 < ksteps) {
-      if (PF == 1 || cur == 1)
-        stg[0].store(sm[cur ^ 1], tid);
-      else
-        stg[PF - 1].store(sm[cur ^ 1], tid);
-    }
+  };
+  if constexpr (PF == 1) {
+    load(stg[0], 0);
+    stg[0].store(sm[0], tid);
     __syncthreads();
+    for (int64_t ks = 0; ks < ksteps; ++ks) {
+      const int cur = ks & 1;
+      if (ks + 1 < ksteps) load(stg[0], ks + 1);
+      compute(sm[cur], ks);
+      if (ks + 1 < ksteps) stg[0].store(sm[cur ^ 1], tid);
+      __syncthreads();
+    }
+  } else {
+    // Two register sets, each k-step loaded two steps ahead; the loop is
+    // unrolled by two so that each half names its sets statically.  Loads past
+    // the end repeat the last k-step (in bounds; staged into a buffer that is
+    // not read again), so every half has the same shape.
+    load(stg[0], 0);
+    load(stg[PF - 1], last < 1 ? last : 1);
+    stg[0].store(sm[0], tid);
+    __syncthreads();
+    for (int64_t ks = 0; ks < ksteps; ks += 2) {
+      load(stg[0], ks + 2 < last ? ks + 2 : last);
+      compute(sm[0], ks);
+      stg[PF - 1].store(sm[1], tid);  // k-step ks + 1
+      __syncthreads();
+      if (ks + 1 >= ksteps) break;
+      load(stg[PF - 1], ks + 3 < last ? ks + 3 : last);
+      compute(sm[1], ks + 1);
+      stg[0].store(sm[0], tid);       // k-step ks + 2
+      __syncthreads();
+    }
   }
-  unsigned char* __restrict__ Z = g.z + (int64_t)mod * g.Mp * g.Np;
+  crt_store_residues<TM, TN, WM, WN>(g, acc, mod, p, m0 + wm * WM, n0 + wn * WN, lane);
+}
+
+// The same product with the k-steps copied straight from global memory into
+// LDS (global_load_lds_dwordx4: lane l of a wavefront lands 16 bytes at the
+// uniform LDS base + 16 l), NS stages deep, so NS - 1 k-steps are in flight
+// without holding registers.  One stage is the tile's BM + BN rows of one
+// k-step; a wavefront copies 16 rows (1 KB) per instruction, lane l taking
+// row l/4 and the global chunk that the row's swizzle puts in slot l%4.
+// Waits: a wavefront's own copies of k-step ks are complete once at most the
+// CPW (NS - 2) copies issued after them are outstanding (vmcnt), and the barrier
+// that follows makes every wavefront's copies visible and frees the stage
+// computed in the previous step.  Copies past the last k-step repeat it into
+// that freed stage, which is not read again, so every step has the same shape.
+template <int BM, int BN, int WGM, int WGN, int NS>
+__global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_dma_kernel(CrtGemmArgs g) {
+  constexpr int BK = kCrtBK;
+  constexpr int NW = WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int STAGE = (BM + BN) * BK;          // bytes per stage
+  constexpr int CH = (BM + BN) / 16;             // 1 KB copies per stage
+  static_assert(CH % NW == 0 && BM % 16 == 0, "whole copies per wavefront, none straddling A and B");
+  constexpr int CPW = CH / NW;                   // copies per wavefront per k-step
+  static_assert(CPW * (NS - 2) <= 15, "wait count fits the vmcnt field");
+  extern __shared__ __attribute__((aligned(16))) signed char dsm[];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  int mod, p;
+  int64_t m0, n0;
+  crt_tile_of(g, BM, BN, &mod, &p, &m0, &n0);
+  const signed char* __restrict__ PA = g.pa + (int64_t)mod * g.Mp * g.Kp + m0 * BK;
+  const signed char* __restrict__ PB = g.pb + (int64_t)mod * g.Np * g.Kp + n0 * BK;
+  const int64_t kstepA = g.Mp * BK, kstepB = g.Np * BK;
+  auto lds_off = [](int r, int q) { return r * BK + ((q ^ ((r >> 2) & 3)) << 4); };
+  // this lane's source offset within each of its copies (rows 16c .. 16c+15)
+  int src[CPW];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int c = wave + NW * j;
+    const int r = 16 * c + (lane >> 2);
+    const int q = (lane & 3) ^ ((r >> 2) & 3);
+    src[j] = (r < BM ? r : r - BM) * BK + q * 16;
+  }
+  auto issue = [&](int64_t ks, int stage) {
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int c = wave + NW * j;
+      const signed char* base = 16 * c < BM ? PA + ks * kstepA : PB + ks * kstepB;
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(base + src[j]),
+                                       (void __attribute__((address_space(3)))*)(dsm + stage * STAGE + c * 1024),
+                                       16, 0, 0);
+    }
+  };
+  i4 acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int64_t m = m0 + wm * WM + i * 16 + fq * 4;
-      const int64_t n = n0 + wn * WN + j * 16 + fr;
-      unsigned word = 0;
+    for (int j = 0; j < TN; ++j) acc[i][j] = i4{0, 0, 0, 0};
+  constexpr int64_t kReduce = 65536 / BK;
+  const int64_t ksteps = g.Kp / BK, last = ksteps - 1;
+  const int fr = lane & 15, fq = lane >> 4;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int v = acc[i][j][r] % p;
-        v += v < 0 ? p : 0;
-        word |= (unsigned)v << (8 * r);
-      }
-      if (g.zt) {
+  for (int s = 0; s < NS - 1; ++s) issue(s < last ? s : last, s);
+  for (int64_t ks = 0; ks < ksteps; ++ks) {
+    // vmcnt <= CPW (NS - 2): simm16 = vmcnt[3:0] | expcnt 7 << 4 | lgkmcnt 15 << 8.
+    // A bare s_barrier, not __syncthreads(): its workgroup fence would wait for
+    // every copy in flight.  The empty asm keeps the compiler from moving LDS
+    // reads above the barrier.
+    __builtin_amdgcn_s_waitcnt((CPW * (NS - 2)) | (7 << 4) | (15 << 8));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    const int64_t nk = ks + NS - 1;
+    issue(nk < last ? nk : last, (int)(nk % NS));
+    const signed char* st = dsm + (ks % NS) * STAGE;
+    i4 af[TM], bfr[TN];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Z[(m + r) * g.Np + n] = (unsigned char)(word >> (8 * r));
-      } else {
-        *reinterpret_cast<unsigned*>(Z + n * g.Mp + m) = word;
-      }
+    for (int i = 0; i < TM; ++i) af[i] = *(const i4*)(st + lds_off(wm * WM + i * 16 + fr, fq));
+#pragma unroll
+    for (int j = 0; j < TN; ++j) bfr[j] = *(const i4*)(st + lds_off(BM + wn * WN + j * 16 + fr, fq));
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    if ((ks + 1) % kReduce == 0) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] %= p;
     }
+  }
+  // the repeated copies of the tail must land before the workgroup's LDS is released
+  __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
+  crt_store_residues<TM, TN, WM, WN>(g, acc, mod, p, m0 + wm * WM, n0 + wn * WN, lane);
 }
 
 // Chinese-remainder rebuild: with M_i = P / p_i and w_i = M_i (M_i^-1 mod p_i)
@@ -771,6 +909,27 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(const unsigned char* _
   }
 }
 
+// Residue GEMM launch: register-staged (pf 1 or 2 k-steps in flight) or
+// copied straight into an LDS ring of pf stages (dynamic LDS beyond 64 KB,
+// allowed once per kernel).
+template <int BM, int BN, int WGM, int WGN, int PF>
+hipError_t launch_crt_gemm(const CrtGemmArgs& g, unsigned blocks, hipStream_t s) {
+  if constexpr (PF <= 2) {
+    hipLaunchKernelGGL((crt_gemm_kernel<BM, BN, WGM, WGN, PF>), dim3(blocks), dim3(64 * WGM * WGN), 0, s, g);
+  } else {
+    constexpr int bytes = PF * (BM + BN) * kCrtBK;
+    static bool allowed = false;  // set once per process; every call makes the same request
+    if (!allowed) {
+      const hipError_t e = hipFuncSetAttribute((const void*)crt_gemm_dma_kernel<BM, BN, WGM, WGN, PF>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+      if (e != hipSuccess) return e;
+      allowed = true;
+    }
+    hipLaunchKernelGGL((crt_gemm_dma_kernel<BM, BN, WGM, WGN, PF>), dim3(blocks), dim3(64 * WGM * WGN), bytes, s, g);
+  }
+  return hipGetLastError();
+}
+
 // Row scales of one input: one wavefront per row when k is stride-1 (and
 // rows are not), else per-segment maxima and a fixed-order second pass.
 hipError_t launch_row_scales(const double* X, Offs xr, Offs xk, int64_t R, int64_t K, int64_t Rp, double* sigma,
@@ -834,13 +993,15 @@ hipError_t launch_crt(const SplitParams& sp, hipStream_t s) {
   const int64_t gblocks = (sp.Mp / t.bm) * (sp.Np / t.bn) * n;
   if (gblocks > kMaxBlocks) return hipErrorInvalidConfiguration;
   switch (sp.crt_tile) {
-#define TC_CRT_LAUNCH(id, bm, bn, wgm, wgn, pf)                                                         \
-  case id:                                                                                            \
-    hipLaunchKernelGGL((crt_gemm_kernel<bm, bn, wgm, wgn, pf>), dim3((unsigned)gblocks), dim3(64 * wgm * wgn), 0, s, g); \
+#define TC_CRT_LAUNCH(id, bm, bn, wgm, wgn, pf)                         \
+  case id:                                                            \
+    e = launch_crt_gemm<bm, bn, wgm, wgn, pf>(g, (unsigned)gblocks, s); \
     break;
     TC_CRT_TILES(TC_CRT_LAUNCH)
 #undef TC_CRT_LAUNCH
+    default: return hipErrorInvalidValue;
   }
+  if (e != hipSuccess) return e;
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // weights: M_i as the product of the other moduli (no 128-bit division)

@@ -280,6 +280,14 @@ def test_crt_plan_bits_and_limits():
         with pytest.raises(tc.TCError) as err:
             analyze("ik", "kj", "ij", ext, precision="crt_int8", split_slices=n)
         assert err.value.status == tc.TC_ERR_INVALID_ARG
+    # residue GEMM configurations: tile_id picks one, -1 the default, others are rejected
+    assert analyze("ik", "kj", "ij", ext, precision="crt_int8", tile_id=2).tile_id == 2
+    assert 0 <= info.tile_id < tc.CRT_NUM_TILES
+    with pytest.raises(tc.TCError) as err:
+        analyze("ik", "kj", "ij", ext, precision="crt_int8", tile_id=tc.CRT_NUM_TILES)
+    assert err.value.status == tc.TC_ERR_INVALID_ARG
+    header = open(HEADER).read()
+    assert re.search(r"#define TC_CRT_NUM_TILES %d\b" % tc.CRT_NUM_TILES, header)
     # the digit forms report their bits too: 8 + 9 (S - 1) for BF16, 4 + 5 (S - 1) for FP8
     assert analyze("ik", "kj", "ij", ext, precision="split_bf16").split_bits == 44
     assert analyze("ik", "kj", "ij", ext, precision="split_fp8").split_bits == 39

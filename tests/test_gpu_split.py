@@ -35,13 +35,13 @@ CASES = [
 ]
 
 
-def _run(labA, labB, labC, A, B, precision, slices=0, alpha=1.0, beta=0.0, C0=None):
+def _run(labA, labB, labC, A, B, precision, slices=0, alpha=1.0, beta=0.0, C0=None, tile=-1):
     dA, dB = to_dev(A), to_dev(B)
     shape = [dict(zip(labA, A.shape), **dict(zip(labB, B.shape)))[l] for l in labC]
     C = colmajor_zeros(shape)
     if C0 is not None:
         C.copy_(to_dev(C0))
-    plan = tc.Plan.for_tensors(dA, labA, dB, labB, C, labC, precision=precision, split_slices=slices)
+    plan = tc.Plan.for_tensors(dA, labA, dB, labB, C, labC, precision=precision, split_slices=slices, tile_id=tile)
     plan.execute(dA, dB, C, alpha, beta)
     torch.cuda.synchronize()
     info = plan.info.as_dict()
@@ -82,6 +82,23 @@ def test_crt_default_meets_1e10(case, kind):
     print(name, kind, "crt %d moduli, %d bits: componentwise error %.3e" % (info["split_slices"], info["split_bits"], err))
     assert info["split_slices"] == 13 and info["split_bits"] >= 42
     assert err <= SPLIT_TOL
+
+
+@pytest.mark.parametrize("tile", range(tc.CRT_NUM_TILES))
+def test_crt_every_gemm_configuration(tile):
+    """Every residue GEMM configuration (register-staged and LDS-ring) on a
+    shape with ragged rows, columns and a contracted range of several
+    k-steps: exact on integers, within the bound on real inputs."""
+    labA, labB, labC = "ikm", "kj", "ijm"
+    ext = {"i": 150, "k": 300, "m": 3, "j": 301}
+    A, B = synth.make_operands(30, labA, labB, ext, kind="integers")
+    got, info = _run(labA, labB, labC, A, B, "crt_int8", tile=tile)
+    assert info["tile_id"] == tile
+    assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
+    A, B = synth.make_operands(31, labA, labB, ext, kind="uniform")
+    got, info = _run(labA, labB, labC, A, B, "crt_int8", tile=tile)
+    ref, absr = reference(A, labA, B, labB, labC)
+    assert componentwise_error(got, ref, absr) <= SPLIT_TOL
 
 
 def test_crt_error_falls_with_moduli():
