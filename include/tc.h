@@ -68,7 +68,7 @@ typedef enum {
 } tc_precision;
 
 /* Residue GEMM configurations of TC_PREC_F64_CRT_INT8 plans (tc_options.tile_id). */
-#define TC_CRT_NUM_TILES 10
+#define TC_CRT_NUM_TILES 12
 
 /* Recipes of Sec. 3.2.  AUTO takes the class's recipe (3.2 -> GEMM, 3.1 ->
  * COPY_GEMM, 2 -> GEMV, 1 -> DOT, no contracted index -> GER); any other

@@ -39,7 +39,7 @@ for _i, _n in enumerate(STATUS_NAMES):
 TC_PREC_F64, TC_PREC_F64_SPLIT_BF16, TC_PREC_F64_SPLIT_FP8, TC_PREC_F64_CRT_INT8 = 0, 1, 2, 3
 PRECISIONS = {"f64": 0, "split_bf16": 1, "split_fp8": 2, "crt_int8": 3}
 # residue-GEMM configurations of TC_PREC_F64_CRT_INT8 plans (tile_id 0 .. CRT_NUM_TILES-1)
-CRT_NUM_TILES = 10
+CRT_NUM_TILES = 12
 # tc_recipe
 TC_RECIPE_AUTO, TC_RECIPE_GEMM, TC_RECIPE_COPY_GEMM, TC_RECIPE_GEMV, TC_RECIPE_GER, TC_RECIPE_DOT = range(6)
 RECIPES = {"auto": 0, "gemm": 1, "copy_gemm": 2, "gemv": 3, "ger": 4, "dot": 5}

@@ -207,7 +207,9 @@ constexpr int kCrtModuli[kCrtMaxModuli] = {256, 255, 253, 251, 247, 241, 239, 23
   X(6, 256, 256, 4, 4, 1)       \
   X(7, 256, 256, 4, 4, 3)       \
   X(8, 256, 256, 4, 4, 4)       \
-  X(9, 256, 128, 4, 2, 4)
+  X(9, 256, 128, 4, 2, 4)       \
+  X(10, 256, 256, 2, 4, 4)      \
+  X(11, 256, 256, 4, 2, 4)
 struct CrtTileCfg {
   int bm, bn, wgm, wgn, pf;
 };

@@ -584,6 +584,11 @@ struct CrtGemmArgs {
   int p[kCrtMaxModuli];
 };
 
+// LDS slot of 16-byte chunk q (of 4) of staged row r (64 bytes) in the
+// register-staged kernels is q ^ crt_swizzle(r): the 16 rows of one fragment
+// read fall in 16 distinct 16-byte bank groups.
+TC_DEV int crt_swizzle(int r) { return (r >> 2) & 3; }
+
 // Product residues z = Z mod p in [0, p) of one wavefront's TM x TN
 // fragments (rows from mw, columns from nw), one byte per output.
 template <int TM, int TN, int WM, int WN>
@@ -656,9 +661,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_kernel(CrtGemmArgs g)
 
   const signed char* __restrict__ PA = g.pa + (int64_t)mod * g.Mp * g.Kp;
   const signed char* __restrict__ PB = g.pb + (int64_t)mod * g.Np * g.Kp;
-  // chunk q of staged row r sits at slot q ^ ((r >> 2) & 3): the 16 rows of
-  // one fragment read fall in 16 distinct 16-byte bank groups
-  auto lds_off = [](int r, int q) { return r * BK + ((q ^ ((r >> 2) & 3)) << 4); };
+  auto lds_off = [](int r, int q) { return r * BK + ((q ^ crt_swizzle(r)) << 4); };
   KStager<CPT, CHUNKS, NT, BM * CPR> stg[PF];
   int soff[CPT];
 #pragma unroll
@@ -745,8 +748,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_kernel(CrtGemmArgs g)
 // LDS (global_load_lds_dwordx4: lane l of a wavefront lands 16 bytes at the
 // uniform LDS base + 16 l), NS stages deep, so NS - 1 k-steps are in flight
 // without holding registers.  One stage is the tile's BM + BN rows of one
-// k-step; a wavefront copies 16 rows (1 KB) per instruction, lane l taking
-// row l/4 and the global chunk that the row's swizzle puts in slot l%4.
+// k-step, stored in fragment order: the 16 rows of group g take 1 KB at
+// 1024 g, chunk q (of 4) of row 16 g + j at 256 q + 16 j.  A fragment read
+// (lane l: row l%16 of the group, chunk l/16) is then one contiguous 1 KB, free
+// of bank conflicts however the LDS groups lanes, and a wavefront's copy of
+// group g (lane l fetching that same row and chunk) is one instruction.
 // Waits: a wavefront's own copies of k-step ks are complete once at most the
 // CPW (NS - 2) copies issued after them are outstanding (vmcnt), and the barrier
 // that follows makes every wavefront's copies visible and frees the stage
@@ -773,14 +779,15 @@ __global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_dma_kernel(CrtGemmArg
   const signed char* __restrict__ PA = g.pa + (int64_t)mod * g.Mp * g.Kp + m0 * BK;
   const signed char* __restrict__ PB = g.pb + (int64_t)mod * g.Np * g.Kp + n0 * BK;
   const int64_t kstepA = g.Mp * BK, kstepB = g.Np * BK;
-  auto lds_off = [](int r, int q) { return r * BK + ((q ^ ((r >> 2) & 3)) << 4); };
+  // fragment-order offset of (row group base b, lane l): 64 b + 16 l
+  auto frag_off = [](int b, int l) { return b * BK + l * 16; };
   // this lane's source offset within each of its copies (rows 16c .. 16c+15)
   int src[CPW];
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
     const int c = wave + NW * j;
-    const int r = 16 * c + (lane >> 2);
-    const int q = (lane & 3) ^ ((r >> 2) & 3);
+    const int r = 16 * c + (lane & 15);
+    const int q = lane >> 4;
     src[j] = (r < BM ? r : r - BM) * BK + q * 16;
   }
   auto issue = [&](int64_t ks, int stage) {
@@ -800,7 +807,6 @@ __global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_dma_kernel(CrtGemmArg
     for (int j = 0; j < TN; ++j) acc[i][j] = i4{0, 0, 0, 0};
   constexpr int64_t kReduce = 65536 / BK;
   const int64_t ksteps = g.Kp / BK, last = ksteps - 1;
-  const int fr = lane & 15, fq = lane >> 4;
 #pragma unroll
   for (int s = 0; s < NS - 1; ++s) issue(s < last ? s : last, s);
   for (int64_t ks = 0; ks < ksteps; ++ks) {
@@ -816,9 +822,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_dma_kernel(CrtGemmArg
     const signed char* st = dsm + (ks % NS) * STAGE;
     i4 af[TM], bfr[TN];
 #pragma unroll
-    for (int i = 0; i < TM; ++i) af[i] = *(const i4*)(st + lds_off(wm * WM + i * 16 + fr, fq));
+    for (int i = 0; i < TM; ++i) af[i] = *(const i4*)(st + frag_off(wm * WM + i * 16, lane));
 #pragma unroll
-    for (int j = 0; j < TN; ++j) bfr[j] = *(const i4*)(st + lds_off(BM + wn * WN + j * 16 + fr, fq));
+    for (int j = 0; j < TN; ++j) bfr[j] = *(const i4*)(st + frag_off(BM + wn * WN + j * 16, lane));
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
