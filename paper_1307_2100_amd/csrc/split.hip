@@ -118,24 +118,50 @@ __device__ inline unsigned char e4m3_of_small_int(int v) {
 // Digits of a 64 x 64 tile of X staged in LDS; rows beyond R and columns
 // beyond K are written as zero digits.
 // Stage the 64 x 64 tile of X at (r0, k0) in LDS, lanes along whichever of
-// r and k is stride-1 in memory (zeros beyond R and K).  256 threads.
+// r and k is stride-1 in memory (zeros beyond R and K).  256 threads.  The
+// offsets of a thread's 16 entries are formed first (one branch on table or
+// stride for the whole tile) and the 16 loads are unconditional (out-of-range
+// entries read X[0] and are replaced by zero), so all of them are in flight
+// together instead of one per basic block.
 TC_DEV void gather_tile64(const double* __restrict__ X, const Offs& xr, const Offs& xk, int64_t R, int64_t K,
                           int64_t r0, int64_t k0, int rfast, double (*tile)[65]) {
   const int tid = threadIdx.x;
-  if (rfast) {
-#pragma unroll 4
-    for (int i = 0; i < 16; ++i) {
-      const int rr = tid & 63, kk = (tid >> 6) + 4 * i;
-      const int64_t r = r0 + rr, k = k0 + kk;
-      tile[rr][kk] = (r < R && k < K) ? X[off_at(xr, r) + off_at(xk, k)] : 0.0;
-    }
+  const int lane64 = tid & 63, q = tid >> 6;
+  double v[16];
+  if (R <= 0 || K <= 0) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = 0.0;
   } else {
-#pragma unroll 4
-    for (int i = 0; i < 16; ++i) {
-      const int kk = tid & 63, rr = (tid >> 6) + 4 * i;
-      const int64_t r = r0 + rr, k = k0 + kk;
-      tile[rr][kk] = (r < R && k < K) ? X[off_at(xr, r) + off_at(xk, k)] : 0.0;
+    // the fixed index (one per thread) and the 16 varying ones
+    const Offs& fixo = rfast ? xr : xk;
+    const Offs& varo = rfast ? xk : xr;
+    const int64_t fix = (rfast ? r0 : k0) + lane64, fixn = rfast ? R : K;
+    const int64_t var0 = rfast ? k0 : r0, varn = rfast ? K : R;
+    const int64_t fo = fix < fixn ? off_at(fixo, fix) : 0;
+    int64_t vo[16];
+    if (varo.tab) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int64_t j = var0 + q + 4 * i;
+        vo[i] = varo.tab[j < varn ? j : 0];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) vo[i] = (var0 + q + 4 * i) * varo.stride;
     }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const bool ok = fix < fixn && var0 + q + 4 * i < varn;
+      const double x = X[ok ? fo + vo[i] : 0];
+      v[i] = ok ? x : 0.0;
+    }
+  }
+  if (rfast) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) tile[lane64][q + 4 * i] = v[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) tile[q + 4 * i][lane64] = v[i];
   }
 }
 
