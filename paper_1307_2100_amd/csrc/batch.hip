@@ -78,7 +78,7 @@ TC_DEV void batch_lanes_k(const BatchItem& it, const GettParams& p, const BatchT
   const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
   const int64_t k0 = (int64_t)s * it.seg_len;
   const int64_t k1 = k0 + it.seg_len < p.K ? k0 + it.seg_len : p.K;
-  const double v = batch_wave_sum(lanes_k_dot<8>(A, B, p.aK, p.bK, k0, k1, lane));
+  const double v = batch_wave_sum(lanes_k_dot_flat<8>(A, B, p.aK, p.bK, k0, k1, lane));
   if (S == 1) {
     if (lane == 0) batch_store(p, m, n, l, v);
     return;
@@ -122,7 +122,7 @@ TC_DEV void batch_lanes_out(const BatchItem& it, const GettParams& p, const Batc
     const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
     const int64_t k0 = (int64_t)task.seg * it.seg_len;
     const int64_t k1 = k0 + it.seg_len < p.K ? k0 + it.seg_len : p.K;
-    v = lanes_out_dot(A, B, p.aK, p.bK, k0, k1);
+    v = lanes_out_dot_flat(A, B, p.aK, p.bK, k0, k1);
   }
   if (S == 1) {
     if (o < outputs) batch_store(p, m, n, l, v);

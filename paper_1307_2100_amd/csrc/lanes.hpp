@@ -110,4 +110,103 @@ TC_DEV double lanes_out_dot(const double* __restrict__ A, const double* __restri
   return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
+// Branch-free forms of the generic (offset-table) loops for the persistent
+// batch kernel: whether each operand goes through a table or a stride is
+// decided once, outside the loop (TA, TB), and steps past the end read
+// offset index k0 and are masked out of the sums instead of skipping their
+// loads, so every load of a step is in flight together.  The sums are the
+// same, in the same order, as in the loops above.
+template <int U, bool TA, bool TB>
+TC_DEV double lanes_k_steps(const double* __restrict__ A, const double* __restrict__ B, const Offs& aK,
+                            const Offs& bK, int64_t k0, int64_t k1, int lane) {
+  auto offa = [&](int64_t kk) { return TA ? aK.tab[kk] : kk * aK.stride; };
+  auto offb = [&](int64_t kk) { return TB ? bK.tab[kk] : kk * bK.stride; };
+  double accu[U];
+  int64_t oa[U], ob[U];
+  int64_t k = k0 + lane;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    accu[u] = 0.0;
+    const int64_t kk = k + 64 * u < k1 ? k + 64 * u : k0;
+    oa[u] = offa(kk);
+    ob[u] = offb(kk);
+  }
+  for (; k < k1; k += 64 * U) {
+    double a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a[u] = A[oa[u]];
+      b[u] = B[ob[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t kn = k + 64 * U + 64 * u;
+      const int64_t kk = kn < k1 ? kn : k0;
+      oa[u] = offa(kk);
+      ob[u] = offb(kk);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) accu[u] += k + 64 * u < k1 ? a[u] * b[u] : 0.0;
+  }
+#pragma unroll
+  for (int w = U / 2; w >= 1; w /= 2)
+#pragma unroll
+    for (int u = 0; u < w; ++u) accu[u] += accu[u + w];
+  return accu[0];
+}
+
+template <int U>
+TC_DEV double lanes_k_dot_flat(const double* __restrict__ A, const double* __restrict__ B, const Offs& aK,
+                               const Offs& bK, int64_t k0, int64_t k1, int lane) {
+  const bool unit = !aK.tab && !bK.tab && aK.stride == 1 && bK.stride == 1;
+  if ((unit && ((reinterpret_cast<uintptr_t>(A + k0) | reinterpret_cast<uintptr_t>(B + k0)) & 15) == 0) || k0 >= k1)
+    return lanes_k_dot<U>(A, B, aK, bK, k0, k1, lane);
+  if (aK.tab)
+    return bK.tab ? lanes_k_steps<U, true, true>(A, B, aK, bK, k0, k1, lane)
+                  : lanes_k_steps<U, true, false>(A, B, aK, bK, k0, k1, lane);
+  return bK.tab ? lanes_k_steps<U, false, true>(A, B, aK, bK, k0, k1, lane)
+                : lanes_k_steps<U, false, false>(A, B, aK, bK, k0, k1, lane);
+}
+
+template <bool TA, bool TB>
+TC_DEV double lanes_out_steps(const double* __restrict__ A, const double* __restrict__ B, const Offs& aK,
+                              const Offs& bK, int64_t k0, int64_t k1) {
+  auto offa = [&](int64_t kk) { return TA ? aK.tab[kk] : kk * aK.stride; };
+  auto offb = [&](int64_t kk) { return TB ? bK.tab[kk] : kk * bK.stride; };
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t oa[4], ob[4];
+  int64_t k = k0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t kk = k + u < k1 ? k + u : k0;
+    oa[u] = offa(kk);
+    ob[u] = offb(kk);
+  }
+  for (; k < k1; k += 4) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = A[oa[u]];
+      b[u] = B[ob[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t kk = k + 4 + u < k1 ? k + 4 + u : k0;
+      oa[u] = offa(kk);
+      ob[u] = offb(kk);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += k + u < k1 ? a[u] * b[u] : 0.0;
+  }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+TC_DEV double lanes_out_dot_flat(const double* __restrict__ A, const double* __restrict__ B, const Offs& aK,
+                                 const Offs& bK, int64_t k0, int64_t k1) {
+  if (k0 >= k1) return 0.0;
+  if (aK.tab)
+    return bK.tab ? lanes_out_steps<true, true>(A, B, aK, bK, k0, k1) : lanes_out_steps<true, false>(A, B, aK, bK, k0, k1);
+  return bK.tab ? lanes_out_steps<false, true>(A, B, aK, bK, k0, k1) : lanes_out_steps<false, false>(A, B, aK, bK, k0, k1);
+}
+
 }  // namespace tc
