@@ -120,6 +120,8 @@ typedef struct {
   int picked_candidate;        /* candidate chosen by the MLP or the tune cache, -1: rules */
   int split_bits;              /* split precision: bits each input keeps relative to its row's power-of-two
                                   scale (every input is exact to 2^-split_bits of that scale), 0 otherwise */
+  int copy_fed;                /* 1: the GEMM runs the kernel fed by direct global-to-LDS copies (operand
+                                  layouts allow 16-byte pairs; taken when A and B are 16-byte aligned) */
 } tc_plan_info;
 
 /* Fills *opt with the defaults listed in tc_options. */

@@ -66,7 +66,8 @@ class tc_plan_info(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t), ("precision", ctypes.c_int),
                 ("split_slices", ctypes.c_int), ("kernel", ctypes.c_int),
-                ("k_split", ctypes.c_int), ("picked_candidate", ctypes.c_int), ("split_bits", ctypes.c_int)]
+                ("k_split", ctypes.c_int), ("picked_candidate", ctypes.c_int), ("split_bits", ctypes.c_int),
+                ("copy_fed", ctypes.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -813,7 +813,9 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
   }
   int tile = info.tile_id >= 0 ? info.tile_id : 1;
   double* parts = info.k_split > 1 ? (double*)((char*)workspace + an.part_offset) : nullptr;
-  e = tc::launch_gett_f64(gp, tile, an.a_kfast, an.b_kfast, info.k_split, an.seg_len, parts, s);
+  // the copy-fed kernel needs the caller's operands (no COPY step) on 16-byte boundaries
+  const bool dma = an.dma_ok && an.copy_slot < 0 && ((reinterpret_cast<uintptr_t>(KA) | reinterpret_cast<uintptr_t>(KB)) & 15) == 0;
+  e = tc::launch_gett_f64(gp, tile, an.a_kfast, an.b_kfast, info.k_split, an.seg_len, parts, s, dma);
   if (e != hipSuccess) return hip_fail(e, "gett launch");
   return TC_OK;
 }

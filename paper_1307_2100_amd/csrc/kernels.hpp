@@ -108,10 +108,15 @@ constexpr TileCfg kTiles[] = {TC_GETT_TILES(TC_TILE_ENTRY)};
 #undef TC_TILE_ENTRY
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
+// The tile whose layout-eligible launches (see Analysis::dma_ok) run the
+// copy-fed kernel.
+constexpr int kDmaTile = 11;
 // split > 1: the contracted range is cut into `split` segments of seg_len
 // (a multiple of the tile depth); parts holds tiles * split * BM * BN doubles.
+// dma: the operands qualify for the copy-fed kernel (used for kDmaTile
+// without split).
 hipError_t launch_gett_f64(const GettParams& p, int tile_id, bool a_kfast, bool b_kfast, int split, int64_t seg_len,
-                           double* parts, hipStream_t s);
+                           double* parts, hipStream_t s, bool dma = false);
 // Split-K choice for `tiles` output tiles of depth-`bk` steps over K.
 inline void choose_split(int64_t tiles, int64_t K, int bk, int* split, int64_t* seg_len) {
   *split = 1;

@@ -338,6 +338,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
   info.k_split = 1;
   info.picked_candidate = -1;
   info.split_bits = 0;
+  info.copy_fed = 0;
   info.unit_a = unit_mode(A0);
   info.unit_b = unit_mode(B0);
   info.unit_c = unit_mode(C0);
@@ -488,6 +489,19 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
   an.b_kfast = !b_nfast && G[GK].n > 0 && G[GK].str[SB][0] == 1;
   an.a_mfast = a_mfast;
   an.b_nfast = b_nfast;
+  {
+    // 16-byte pairs along each operand's stride-1 mode (see Analysis::dma_ok)
+    auto pairs = [&](int slot, int rowg, bool rowfast, bool kfast) {
+      if (!rowfast && !kfast) return false;
+      const int lead = rowfast ? rowg : GK;
+      if (G[lead].ext[0] % 2 != 0) return false;
+      for (int g : {rowg, (int)GK, (int)GL})
+        for (int i = 0; i < G[g].n; ++i)
+          if (!(g == lead && i == 0) && G[g].str[slot][i] % 2 != 0) return false;
+      return true;
+    };
+    an.dma_ok = G[GK].n == 1 && pairs(SA, GM, a_mfast, an.a_kfast) && pairs(SB, GN, b_nfast, an.b_kfast);
+  }
 
   info.M = G[GM].size();
   info.N = G[GN].size();
@@ -582,6 +596,8 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
       an.part_offset = (info.workspace_bytes + 255) / 256 * 256;
       info.workspace_bytes = an.part_offset + (size_t)tiles * split * t.bm * t.bn * sizeof(double);
     }
+    an.dma_ok = an.dma_ok && recipe == TC_RECIPE_GEMM && split == 1 && info.tile_id == kDmaTile;
+    info.copy_fed = an.dma_ok ? 1 : 0;
   } else {
     // Memory-bound recipes (Sec. 3.2, Classes 1 and 2, and the GER slicing).
     // GER sums its rank-1 updates in registers, one thread per output entry.

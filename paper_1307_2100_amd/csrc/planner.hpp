@@ -66,6 +66,10 @@ struct Analysis {
   int64_t seg_len = 0;      // split-K GEMM: contracted indices per segment
   bool a_mfast = false;     // kernel A's stride-1 mode leads its free group
   bool b_nfast = false;     // kernel B's stride-1 mode leads its free group
+  // GEMM: both operands can be copied in 16-byte pairs along their stride-1
+  // mode (it leads the row or contracted group with an even extent, every
+  // other stride is even) and the contracted group is one affine mode
+  bool dma_ok = false;
   // split precision: padded sizes of the digit planes and workspace offsets
   int slices = 0;
   int crt_bits = 0;         // residue form: bits of the integer inputs

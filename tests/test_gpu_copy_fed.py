@@ -1,0 +1,74 @@
+"""The GEMM kernel fed by direct global-to-LDS copies (taken for the 256 x
+128 tile when every operand can be copied in 16-byte pairs along its
+stride-1 mode) against the oracle: ragged rows, columns and contracted range,
+k-fast and row-fast operands in every combination, a free group addressed
+through an offset table, a batch index, alpha and beta.  Integer inputs must
+match bit for bit; uniform inputs are held to the FP64 bound."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_util import FP64_TOL, colmajor_zeros, componentwise_error, reference, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1307_2100_amd as tc  # noqa: E402
+
+CASES = [
+    # name, labA, labB, labC, extents: every leading extent even, K not a multiple of 16
+    ("cc_a_ragged", "abcd", "cdij", "abij", {"a": 18, "b": 15, "c": 10, "d": 7, "i": 6, "j": 50}),
+    ("both_k_fast", "km", "kn", "mn", {"k": 38, "m": 260, "n": 130}),
+    ("both_row_fast", "mk", "nk", "mn", {"k": 38, "m": 260, "n": 130}),
+    ("table_rows", "kai", "kj", "aji", {"k": 20, "a": 30, "i": 9, "j": 40}),
+    ("batch", "kmb", "knb", "mnb", {"k": 36, "m": 260, "n": 130, "b": 3}),
+    ("short_k", "km", "kn", "mn", {"k": 2, "m": 300, "n": 140}),
+]
+
+
+def _run(labA, labB, labC, A, B, alpha=1.0, beta=0.0, C0=None):
+    dA, dB = to_dev(A), to_dev(B)
+    shape = [dict(zip(labA, A.shape), **dict(zip(labB, B.shape)))[l] for l in labC]
+    C = colmajor_zeros(shape)
+    if C0 is not None:
+        C.copy_(to_dev(C0))
+    plan = tc.Plan.for_tensors(dA, labA, dB, labB, C, labC, recipe="gemm", tile_id=11)
+    info = plan.info.as_dict()
+    plan.execute(dA, dB, C, alpha, beta)
+    torch.cuda.synchronize()
+    plan.close()
+    return C.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_copy_fed_gemm_parity(case):
+    name, labA, labB, labC, ext = case
+    A, B = synth.make_operands(40, labA, labB, ext, kind="integers")
+    got, info = _run(labA, labB, labC, A, B)
+    assert info["copy_fed"] == 1 and info["tile_id"] == 11 and info["k_split"] == 1, info
+    assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
+    A, B = synth.make_operands(41, labA, labB, ext, kind="uniform")
+    got, _ = _run(labA, labB, labC, A, B)
+    ref, absr = reference(A, labA, B, labB, labC)
+    assert componentwise_error(got, ref, absr) <= FP64_TOL
+
+
+def test_copy_fed_alpha_beta():
+    name, labA, labB, labC, ext = CASES[0]
+    A, B = synth.make_operands(42, labA, labB, ext, kind="integers")
+    C0 = synth.integers([ext[l] for l in labC], 43)
+    got, info = _run(labA, labB, labC, A, B, alpha=-2.0, beta=0.5, C0=C0)
+    assert info["copy_fed"] == 1
+    assert np.array_equal(got, -2.0 * oracle.contract(A, labA, B, labB, labC) + 0.5 * C0)
+
+
+def test_odd_leading_extent_keeps_the_gather_kernel():
+    labA, labB, labC, ext = "abcd", "cdij", "abij", {"a": 17, "b": 15, "c": 10, "d": 7, "i": 6, "j": 50}
+    A, B = synth.make_operands(44, labA, labB, ext, kind="integers")
+    got, info = _run(labA, labB, labC, A, B)
+    assert info["copy_fed"] == 0
+    assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
