@@ -815,7 +815,17 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
   double* parts = info.k_split > 1 ? (double*)((char*)workspace + an.part_offset) : nullptr;
   // the copy-fed kernel needs the caller's operands (no COPY step) on 16-byte boundaries
   const bool dma = an.dma_ok && an.copy_slot < 0 && ((reinterpret_cast<uintptr_t>(KA) | reinterpret_cast<uintptr_t>(KB)) & 15) == 0;
-  e = tc::launch_gett_f64(gp, tile, an.a_kfast, an.b_kfast, info.k_split, an.seg_len, parts, s, dma);
+  tc::DmaK dk{};
+  if (dma) {
+    const tc::Group& gk = an.g[tc::GK];
+    dk.n = gk.n;
+    for (int i = 0; i < gk.n && i < tc::kDmaMaxKModes; ++i) {
+      dk.ext[i] = gk.ext[i];
+      dk.sa[i] = gk.str[tc::SA][i];
+      dk.sb[i] = gk.str[tc::SB][i];
+    }
+  }
+  e = tc::launch_gett_f64(gp, tile, an.a_kfast, an.b_kfast, info.k_split, an.seg_len, parts, s, dma ? &dk : nullptr);
   if (e != hipSuccess) return hip_fail(e, "gett launch");
   return TC_OK;
 }

@@ -92,6 +92,8 @@ __global__ __launch_bounds__(256) void gett_reduce_kernel(GettParams p, int64_t 
 //   * row-fast operand, copy h: lane l takes k = 8h + l/8 and rows 2(l%8),
 //     +1, i.e. entry (k, r) at 1024 (k/8) + 128 (k%8) + 8 r; a fragment value
 //     is one 8-byte read.
+// Contracted offsets come from the digits of k over the group's modes (no
+// table lookup in front of a copy).
 // Rows beyond the operand load a clamped in-range row (their results are
 // not stored); contracted indices beyond K load a clamped in-range index and
 // the fragment values of those indices are set to zero in the last k-tile.
@@ -101,8 +103,8 @@ __global__ __launch_bounds__(256) void gett_reduce_kernel(GettParams p, int64_t 
 // of the previous k-tile (a __syncthreads() fence would wait for every copy
 // in flight).  Copies past the last k-tile repeat it into that freed stage.
 template <int BM, int BN, int WGM, int WGN, bool AKF, bool BKF, int NS>
-__global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_dma_kernel(GettParams p, int64_t tilesM, int64_t tilesN,
-                                                                       int64_t total) {
+__global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_dma_kernel(GettParams p, DmaK dk, int64_t tilesM,
+                                                                       int64_t tilesN, int64_t total) {
   constexpr int BK = 16;
   constexpr int NW = WGM * WGN;
   constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -123,7 +125,22 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_dma_kernel(GettParams
   const double* __restrict__ A = p.A + off_at(p.aL, l);
   const double* __restrict__ B = p.B + off_at(p.bL, l);
   const int64_t K = p.K;
-  const int64_t aks = p.aK.stride, bks = p.bK.stride;  // unsliced contracted group: affine
+  // offset of contracted index k in the kernel's A (opb false) or B
+  auto koff = [&](int64_t k, bool opb) {
+    if (dk.n == 1) return k * (opb ? dk.sb[0] : dk.sa[0]);
+    int64_t off = 0;
+    uint32_t rem = (uint32_t)k;
+#pragma unroll
+    for (int i = 0; i < kDmaMaxKModes; ++i) {
+      if (i >= dk.n) break;
+      const uint32_t e = (uint32_t)dk.ext[i];
+      const uint32_t q = i + 1 < dk.n ? rem / e : 0;
+      const uint32_t d = i + 1 < dk.n ? rem - q * e : rem;
+      off += (int64_t)d * (opb ? dk.sb[i] : dk.sa[i]);
+      rem = q;
+    }
+    return off;
+  };
 
   // this lane's part of its wavefront's copies: row offset and k position in the tile
   int64_t roff[CPW];
@@ -142,16 +159,28 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_dma_kernel(GettParams
     roff[j] = off_at(opb ? p.bN : p.aM, r);
     kpos[j] = kf ? 4 * (lane >> 4) + 2 * h : 8 * h + (lane >> 3);
   }
+  // when the first contracted mode spans whole k-tiles, a tile's k digits
+  // above the first are the same for every lane: one (scalar) decomposition
+  // per tile and operand, plus this lane's position along the first mode
+  const bool whole = dk.ext[0] % BK == 0;
   auto issue = [&](int64_t kt, int stage) {
+    const int64_t kb = kt * BK;
+    const int64_t ba = whole ? koff(kb, false) : 0, bb = whole ? koff(kb, true) : 0;
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
       const int c = wave + NW * j;
       const bool opb = c >= 2 * ABLK;
       const bool kf = opb ? BKF : AKF;
-      int64_t k = kt * BK + kpos[j];
+      int64_t k = kb + kpos[j];
       const int64_t kmax = kf ? K - 2 : K - 1;  // k-fast operands have an even K
-      k = k < kmax ? k : kmax;
-      const double* src = opb ? B + roff[j] + k * bks : A + roff[j] + k * aks;
+      int64_t ko;
+      if (whole && k <= kmax) {
+        ko = (opb ? bb : ba) + kpos[j] * (opb ? dk.sb[0] : dk.sa[0]);
+      } else {
+        k = k < kmax ? k : kmax;
+        ko = koff(k, opb);
+      }
+      const double* src = (opb ? B : A) + roff[j] + ko;
       __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
                                        (void __attribute__((address_space(3)))*)(dsm + stage * STAGE + c * 1024),
                                        16, 0, 0);
@@ -260,7 +289,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_dma_kernel(GettParams
 }
 
 template <int BM, int BN, int WGM, int WGN, bool AKF, bool BKF, int NS>
-hipError_t launch_dma_one(const GettParams& p, int64_t tilesM, int64_t tilesN, int64_t total, hipStream_t s) {
+hipError_t launch_dma_one(const GettParams& p, const DmaK& dk, int64_t tilesM, int64_t tilesN, int64_t total,
+                          hipStream_t s) {
   constexpr int bytes = NS * 2 * (BM / 16 + BN / 16) * 1024;
   static bool allowed = false;  // set once per process; every call makes the same request
   if (!allowed) {
@@ -270,21 +300,22 @@ hipError_t launch_dma_one(const GettParams& p, int64_t tilesM, int64_t tilesN, i
     allowed = true;
   }
   hipLaunchKernelGGL((gett_f64_dma_kernel<BM, BN, WGM, WGN, AKF, BKF, NS>), dim3((unsigned)total),
-                     dim3(64 * WGM * WGN), bytes, s, p, tilesM, tilesN, total);
+                     dim3(64 * WGM * WGN), bytes, s, p, dk, tilesM, tilesN, total);
   return hipGetLastError();
 }
 
 template <int BM, int BN, int WGM, int WGN>
-hipError_t launch_dma(const GettParams& p, bool akf, bool bkf, hipStream_t s) {
+hipError_t launch_dma(const GettParams& p, const DmaK& dk, bool akf, bool bkf, hipStream_t s) {
   const int64_t tilesM = (p.M + BM - 1) / BM, tilesN = (p.N + BN - 1) / BN;
   const int64_t total = tilesM * tilesN * p.L;
   if (total == 0) return hipSuccess;
   if (total > 0xffffffffLL / (64 * WGM * WGN)) return hipErrorInvalidConfiguration;
+  if (dk.n < 1 || dk.n > kDmaMaxKModes || p.K > 0x7fffffffLL) return hipErrorInvalidValue;
   constexpr int NS = 3;
-  if (akf && bkf) return launch_dma_one<BM, BN, WGM, WGN, true, true, NS>(p, tilesM, tilesN, total, s);
-  if (akf) return launch_dma_one<BM, BN, WGM, WGN, true, false, NS>(p, tilesM, tilesN, total, s);
-  if (bkf) return launch_dma_one<BM, BN, WGM, WGN, false, true, NS>(p, tilesM, tilesN, total, s);
-  return launch_dma_one<BM, BN, WGM, WGN, false, false, NS>(p, tilesM, tilesN, total, s);
+  if (akf && bkf) return launch_dma_one<BM, BN, WGM, WGN, true, true, NS>(p, dk, tilesM, tilesN, total, s);
+  if (akf) return launch_dma_one<BM, BN, WGM, WGN, true, false, NS>(p, dk, tilesM, tilesN, total, s);
+  if (bkf) return launch_dma_one<BM, BN, WGM, WGN, false, true, NS>(p, dk, tilesM, tilesN, total, s);
+  return launch_dma_one<BM, BN, WGM, WGN, false, false, NS>(p, dk, tilesM, tilesN, total, s);
 }
 
 template <int BM, int BN, int BK, int WGM, int WGN>
@@ -331,13 +362,13 @@ hipError_t launch_cfg(const GettParams& p, bool akf, bool bkf, int S, int64_t se
 }  // namespace
 
 hipError_t launch_gett_f64(const GettParams& p, int tile_id, bool a_kfast, bool b_kfast, int split, int64_t seg_len,
-                           double* parts, hipStream_t s, bool dma) {
+                           double* parts, hipStream_t s, const DmaK* dma) {
   if (dma && split == 1 && tile_id == kDmaTile) {
     // same 256 x 128 x 16 tile, as 8 wavefronts of 64 x 64 (the copies hold no
     // registers, so each wavefront can keep a larger block of C)
     static_assert(kTiles[kDmaTile].bm == 256 && kTiles[kDmaTile].bn == 128 && kTiles[kDmaTile].bk == 16,
                   "the copy-fed kernel is instantiated for this tile");
-    return launch_dma<256, 128, 4, 2>(p, a_kfast, b_kfast, s);
+    return launch_dma<256, 128, 4, 2>(p, *dma, a_kfast, b_kfast, s);
   }
   switch (tile_id) {
 #define TC_TILE(id, bm, bn, bk, wgm, wgn) \

@@ -111,12 +111,22 @@ constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 // The tile whose layout-eligible launches (see Analysis::dma_ok) run the
 // copy-fed kernel.
 constexpr int kDmaTile = 11;
+// Contracted group of the copy-fed kernel as modes (first fastest): the
+// offset of k is computed from its digits, so no table lookup (a dependent
+// load) sits in front of a copy.
+constexpr int kDmaMaxKModes = 4;
+struct DmaK {
+  int n;
+  int64_t ext[kDmaMaxKModes];
+  int64_t sa[kDmaMaxKModes];  // strides in the kernel's A
+  int64_t sb[kDmaMaxKModes];  // strides in the kernel's B
+};
 // split > 1: the contracted range is cut into `split` segments of seg_len
 // (a multiple of the tile depth); parts holds tiles * split * BM * BN doubles.
 // dma: the operands qualify for the copy-fed kernel (used for kDmaTile
 // without split).
 hipError_t launch_gett_f64(const GettParams& p, int tile_id, bool a_kfast, bool b_kfast, int split, int64_t seg_len,
-                           double* parts, hipStream_t s, bool dma = false);
+                           double* parts, hipStream_t s, const DmaK* dma = nullptr);
 // Split-K choice for `tiles` output tiles of depth-`bk` steps over K.
 inline void choose_split(int64_t tiles, int64_t K, int bk, int* split, int64_t* seg_len) {
   *split = 1;

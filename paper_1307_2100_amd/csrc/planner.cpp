@@ -500,7 +500,8 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
           if (!(g == lead && i == 0) && G[g].str[slot][i] % 2 != 0) return false;
       return true;
     };
-    an.dma_ok = G[GK].n == 1 && pairs(SA, GM, a_mfast, an.a_kfast) && pairs(SB, GN, b_nfast, an.b_kfast);
+    an.dma_ok = G[GK].n >= 1 && G[GK].n <= kDmaMaxKModes && G[GK].size() <= 0x7fffffffLL &&
+                pairs(SA, GM, a_mfast, an.a_kfast) && pairs(SB, GN, b_nfast, an.b_kfast);
   }
 
   info.M = G[GM].size();

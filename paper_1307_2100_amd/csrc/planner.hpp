@@ -68,7 +68,8 @@ struct Analysis {
   bool b_nfast = false;     // kernel B's stride-1 mode leads its free group
   // GEMM: both operands can be copied in 16-byte pairs along their stride-1
   // mode (it leads the row or contracted group with an even extent, every
-  // other stride is even) and the contracted group is one affine mode
+  // other stride is even) and the contracted group has at most
+  // kDmaMaxKModes modes
   bool dma_ok = false;
   // split precision: padded sizes of the digit planes and workspace offsets
   int slices = 0;

@@ -2,7 +2,8 @@
 128 tile when every operand can be copied in 16-byte pairs along its
 stride-1 mode) against the oracle: ragged rows, columns and contracted range,
 k-fast and row-fast operands in every combination, a free group addressed
-through an offset table, a batch index, alpha and beta.  Integer inputs must
+through an offset table, contracted groups of several modes, a batch index,
+alpha and beta.  Integer inputs must
 match bit for bit; uniform inputs are held to the FP64 bound."""
 import numpy as np
 import pytest
@@ -27,6 +28,9 @@ CASES = [
     ("table_rows", "kai", "kj", "aji", {"k": 20, "a": 30, "i": 9, "j": 40}),
     ("batch", "kmb", "knb", "mnb", {"k": 36, "m": 260, "n": 130, "b": 3}),
     ("short_k", "km", "kn", "mn", {"k": 2, "m": 300, "n": 140}),
+    # contracted groups of two modes (offsets from the digits of k)
+    ("cc_b_ragged", "akic", "kbcj", "abij", {"a": 14, "k": 6, "i": 5, "c": 18, "b": 22, "j": 9}),
+    ("three_k_modes", "kxmy", "kxny", "mn", {"k": 6, "x": 5, "y": 3, "m": 260, "n": 130}),
 ]
 
 
