@@ -182,7 +182,8 @@ def main():
     achieved = ia.flops / (ms_a * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic_from_profile(GETT_SOURCES),
-                "kernel": "gett_f64_kernel (contraction a)", "algorithmic_flops_per_launch": ia.flops,
+                "kernel": "%s (contraction a)" % ("gett_f64_dma_kernel" if ia.copy_fed else "gett_f64_kernel"),
+                "algorithmic_flops_per_launch": ia.flops,
                 "algorithmic_bytes_per_launch": ia.bytes}
 
     cpu = None
