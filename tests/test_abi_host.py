@@ -294,6 +294,27 @@ def test_crt_plan_bits_and_limits():
     assert analyze("ik", "kj", "ij", ext).split_bits == 0
 
 
+def test_copy_fed_gemm_eligibility():
+    """The copy-fed FP64 kernel is planned for the 256x128 tile (no split-K,
+    no COPY step) when every operand's stride-1 mode leads its row or
+    contracted group with an even extent and every other stride is even."""
+    for la, lb, lc, ext in (synth.workload_cc_a(128, 32), synth.workload_cc_b(128, 32)):
+        info = analyze(la, lb, lc, ext)
+        assert info.tile_id == 11 and info.k_split == 1 and info.copy_fed == 1
+    ext = {"a": 18, "b": 15, "c": 10, "d": 7, "i": 6, "j": 50}
+    assert analyze("abcd", "cdij", "abij", ext, recipe="gemm", tile_id=11).copy_fed == 1
+    assert analyze("abcd", "cdij", "abij", ext, recipe="gemm", tile_id=0).copy_fed == 0       # other tile
+    assert analyze("abcd", "cdij", "abij", ext, recipe="copy_gemm", tile_id=11).copy_fed == 0  # COPY step
+    assert analyze("abcd", "cdij", "abij", ext, precision="crt_int8").copy_fed == 0
+    odd = dict(ext, a=17)                                       # odd leading extent of the row-fast operand
+    assert analyze("abcd", "cdij", "abij", odd, recipe="gemm", tile_id=11).copy_fed == 0
+    oddk = dict(ext, c=9)                                       # odd leading extent of the k-fast operand
+    assert analyze("abcd", "cdij", "abij", oddk, recipe="gemm", tile_id=11).copy_fed == 0
+    # a strided (every other entry) view keeps no stride-1 mode: no 16-byte pairs
+    sA = colmajor_strides([18, 15, 10, 7])
+    assert analyze("abcd", "cdij", "abij", ext, sA=[2 * x for x in sA], recipe="gemm", tile_id=11).copy_fed == 0
+
+
 def test_fast_division_method():
     """The slab engine divides by plan-time constants with a multiply and a
     shift (mul = ceil(2^p / d), p = 31 + ceil(log2 d)); check the method
