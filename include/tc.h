@@ -115,7 +115,7 @@ typedef struct {
   tc_precision precision;
   int split_slices;            /* digits per input (split precision), 0 otherwise */
   int kernel;                  /* kernel family: 0 MFMA GEMM, 1 lanes over outputs, 2 lanes over k,
-                                  3 batched small slabs, 4 split-precision digits */
+                                  3 batched small slabs, 4 split precision (digits or residues) */
   int k_split;                 /* MFMA GEMM: segments of the contracted range (1 = none) */
   int picked_candidate;        /* candidate chosen by the MLP or the tune cache, -1: rules */
   int split_bits;              /* split precision: bits each input keeps relative to its row's power-of-two

@@ -44,7 +44,7 @@ CRT_NUM_TILES = 12
 TC_RECIPE_AUTO, TC_RECIPE_GEMM, TC_RECIPE_COPY_GEMM, TC_RECIPE_GEMV, TC_RECIPE_GER, TC_RECIPE_DOT = range(6)
 RECIPES = {"auto": 0, "gemm": 1, "copy_gemm": 2, "gemv": 3, "ger": 4, "dot": 5}
 RECIPE_NAMES = {v: k for k, v in RECIPES.items()}
-KERNEL_NAMES = {0: "mfma_gemm", 1: "lanes_over_outputs", 2: "lanes_over_k", 3: "batched_small", 4: "split_digits"}
+KERNEL_NAMES = {0: "mfma_gemm", 1: "lanes_over_outputs", 2: "lanes_over_k", 3: "batched_small", 4: "split"}
 # GEMM tile configurations compiled into libtc (ids 0 .. NUM_TILES-1)
 NUM_TILES = 18
 # tc_picker
