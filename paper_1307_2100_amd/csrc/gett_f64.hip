@@ -292,13 +292,10 @@ template <int BM, int BN, int WGM, int WGN, bool AKF, bool BKF, int NS>
 hipError_t launch_dma_one(const GettParams& p, const DmaK& dk, int64_t tilesM, int64_t tilesN, int64_t total,
                           hipStream_t s) {
   constexpr int bytes = NS * 2 * (BM / 16 + BN / 16) * 1024;
-  static bool allowed = false;  // set once per process; every call makes the same request
-  if (!allowed) {
-    const hipError_t e = hipFuncSetAttribute((const void*)gett_f64_dma_kernel<BM, BN, WGM, WGN, AKF, BKF, NS>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    allowed = true;
-  }
+  static std::atomic<uint64_t> allowed{0};
+  const hipError_t e =
+      allow_dynamic_lds((const void*)gett_f64_dma_kernel<BM, BN, WGM, WGN, AKF, BKF, NS>, bytes, allowed);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((gett_f64_dma_kernel<BM, BN, WGM, WGN, AKF, BKF, NS>), dim3((unsigned)total),
                      dim3(64 * WGM * WGN), bytes, s, p, dk, tilesM, tilesN, total);
   return hipGetLastError();

@@ -943,20 +943,16 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(const unsigned char* _
 
 // Residue GEMM launch: register-staged (pf 1 or 2 k-steps in flight) or
 // copied straight into an LDS ring of pf stages (dynamic LDS beyond 64 KB,
-// allowed once per kernel).
+// allowed once per kernel and device).
 template <int BM, int BN, int WGM, int WGN, int PF>
 hipError_t launch_crt_gemm(const CrtGemmArgs& g, unsigned blocks, hipStream_t s) {
   if constexpr (PF <= 2) {
     hipLaunchKernelGGL((crt_gemm_kernel<BM, BN, WGM, WGN, PF>), dim3(blocks), dim3(64 * WGM * WGN), 0, s, g);
   } else {
     constexpr int bytes = PF * (BM + BN) * kCrtBK;
-    static bool allowed = false;  // set once per process; every call makes the same request
-    if (!allowed) {
-      const hipError_t e = hipFuncSetAttribute((const void*)crt_gemm_dma_kernel<BM, BN, WGM, WGN, PF>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-      if (e != hipSuccess) return e;
-      allowed = true;
-    }
+    static std::atomic<uint64_t> allowed{0};
+    const hipError_t e = allow_dynamic_lds((const void*)crt_gemm_dma_kernel<BM, BN, WGM, WGN, PF>, bytes, allowed);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((crt_gemm_dma_kernel<BM, BN, WGM, WGN, PF>), dim3(blocks), dim3(64 * WGM * WGN), bytes, s, g);
   }
   return hipGetLastError();

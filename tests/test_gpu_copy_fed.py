@@ -31,6 +31,9 @@ CASES = [
     # contracted groups of two modes (offsets from the digits of k)
     ("cc_b_ragged", "akic", "kbcj", "abij", {"a": 14, "k": 6, "i": 5, "c": 18, "b": 22, "j": 9}),
     ("three_k_modes", "kxmy", "kxny", "mn", {"k": 6, "x": 5, "y": 3, "m": 260, "n": 130}),
+    # far fewer rows than one tile
+    ("tiny_row_fast", "mk", "nk", "mn", {"k": 34, "m": 2, "n": 4}),
+    ("tiny_k_fast", "km", "kn", "mn", {"k": 34, "m": 3, "n": 1}),
 ]
 
 
