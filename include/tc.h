@@ -94,7 +94,8 @@ typedef struct {
   tc_recipe recipe;            /* default TC_RECIPE_AUTO */
   tc_picker picker;            /* default TC_PICKER_RULES */
   int split_slices;            /* slices per operand for split precision (moduli for TC_PREC_F64_CRT_INT8,
-                                  2 to 14); 0 = default (5 BF16, 8 FP8, 13 moduli) */
+                                  2 to 14); 0 = default (5 BF16, 8 FP8; for residues the fewest moduli
+                                  that keep at least 40 bits per input for the plan's K) */
   int tile_id;                 /* GEMM tile configuration; -1 = chosen by the picker.  For
                                   TC_PREC_F64_CRT_INT8 plans: residue GEMM configuration, 0 to
                                   TC_CRT_NUM_TILES - 1, -1 = the default */

@@ -522,7 +522,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     const bool crt = opt.precision == TC_PREC_F64_CRT_INT8;
     const int maxs = crt ? kCrtMaxModuli : (fp8 ? kSplitMaxFp8 : kSplitMaxBf16);
     int S = opt.split_slices > 0 ? opt.split_slices
-                                 : (crt ? kCrtDefaultModuli : (fp8 ? kSplitDefaultFp8 : kSplitDefaultBf16));
+                                 : (crt ? crt_default_moduli(info.K) : (fp8 ? kSplitDefaultFp8 : kSplitDefaultBf16));
     if (S > maxs || (crt && S < 2)) {
       *err = fmt("split_slices %lld is outside the range %lld to ", S, crt ? 2 : 1) +
              fmt("%lld for this digit type", maxs);

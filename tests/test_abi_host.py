@@ -262,9 +262,15 @@ def test_crt_plan_bits_and_limits():
             P *= p
         return max([b for b in range(1, 49) if 2 * K * 4 ** b < P] or [0])
 
+    def default_moduli(K):
+        return min([n for n in range(2, 15) if expected_bits(n, K) >= 40] or [14])
+
     ext = {"i": 40, "k": 300, "j": 7}
     info = analyze("ik", "kj", "ij", ext, precision="crt_int8")
-    assert info.split_slices == 13 and info.split_bits == expected_bits(13, 300)
+    assert info.split_slices == default_moduli(300) == 12 and info.split_bits == expected_bits(12, 300) >= 40
+    for K in (2, 300, 4096, 16384, 36864, 1 << 20, 1 << 24):
+        i = analyze("ik", "kj", "ij", {"i": 3, "k": K, "j": 2}, precision="crt_int8")
+        assert i.split_slices == default_moduli(K) and i.split_bits == expected_bits(i.split_slices, K)
     assert info.kernel == 4 and info.workspace_bytes > 0 and info.precision == tc.TC_PREC_F64_CRT_INT8
     for n in range(2, 15):
         for K in (1, 4, 300, 4096, 36864, 70000):

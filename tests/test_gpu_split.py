@@ -6,9 +6,9 @@ Integer-valued inputs in [-4, 4] fit in one digit, and in the integer form
 of the residue path, so every product and sum is exact and the result must
 equal the oracle bit for bit.  Otherwise the componentwise error must stay
 within the bound of the bits kept per input: BF16 with the default 5 digits
-(8 + 4x9 = 44 bits) and the residue form with the default 13 moduli (42 to
-52 bits, depending on the contracted extent) are held to 1e-10, also on
-inputs whose slices are scaled by 10^U(-3,3)."""
+(8 + 4x9 = 44 bits) and the residue form with its default moduli (at least
+40 bits) are held to 1e-10, also on inputs whose slices are scaled by
+10^U(-3,3)."""
 import numpy as np
 import pytest
 
@@ -80,7 +80,7 @@ def test_crt_default_meets_1e10(case, kind):
     ref, absr = reference(A, labA, B, labB, labC)
     err = componentwise_error(got, ref, absr)
     print(name, kind, "crt %d moduli, %d bits: componentwise error %.3e" % (info["split_slices"], info["split_bits"], err))
-    assert info["split_slices"] == 13 and info["split_bits"] >= 42
+    assert info["split_bits"] >= 40
     assert err <= SPLIT_TOL
 
 
