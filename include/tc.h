@@ -137,6 +137,31 @@ tc_status tc_analyze(int rank_a, const int64_t* ext_a, const int64_t* str_a, con
                      int rank_c, const int64_t* ext_c, const int64_t* str_c, const int32_t* lab_c,
                      const tc_options* opt, tc_plan_info* info);
 
+/* Host only.  Layout advice of Sec. 3.3 (and the closing remarks of Sec. 5):
+ * storage orders under which the contraction runs as one direct GEMM, with no
+ * copy.  Arguments as tc_analyze, except that any stride array may be NULL
+ * (the tensor is then packed column-major in the listed order); strides
+ * matter only for fixed tensors.  fixed: bit 0 keeps A's storage as given,
+ * bit 1 B's, bit 2 C's.  order_x (rank_x entries, caller-owned) receives the
+ * suggested storage order: order_x[j] is the listed mode of X stored j-th,
+ * j = 0 at stride 1 (for a fixed tensor, its modes by ascending stride).  A
+ * free tensor is stored as A [free-A, contracted, batch], B [contracted,
+ * free-B, batch] (B [free-B, contracted, batch] when A is fixed with a
+ * contracted or batch index at stride 1), C [free-A, free-B, batch]; each
+ * index group keeps one order in all tensors that hold it, taken from a fixed
+ * tensor when there is one.  When both inputs have a free index, A or B is not
+ * fixed and no fixed input has a batch index at stride 1, the suggested
+ * layout is Class 3.2 and each index group of a free tensor is contiguous
+ * (with nothing fixed, every group fuses into one mode).  info (may be NULL) receives
+ * the analysis of the suggested layout with packed strides.  Errors: those of
+ * tc_analyze; TC_ERR_INVALID_ARG for a null order array or fixed outside
+ * 0..7.  Nothing is written to the order arrays on error. */
+tc_status tc_suggest_layout(int rank_a, const int64_t* ext_a, const int64_t* str_a, const int32_t* lab_a,
+                            int rank_b, const int64_t* ext_b, const int64_t* str_b, const int32_t* lab_b,
+                            int rank_c, const int64_t* ext_c, const int64_t* str_c, const int32_t* lab_c,
+                            int fixed, int32_t* order_a, int32_t* order_b, int32_t* order_c,
+                            tc_plan_info* info);
+
 /* Builds an immutable plan for C <- alpha * sum A*B + beta * C (Sec. 2.3;
  * classification and recipe as in Sec. 3.2).  The plan copies the host
  * arrays, builds its index-offset tables and uploads them to the current

@@ -84,6 +84,8 @@ _lib.tc_options_default.argtypes = [ctypes.POINTER(tc_options)]
 _lib.tc_options_default.restype = None
 _lib.tc_analyze.argtypes = _DESC * 3 + [ctypes.POINTER(tc_options), ctypes.POINTER(tc_plan_info)]
 _lib.tc_analyze.restype = ctypes.c_int
+_lib.tc_suggest_layout.argtypes = _DESC * 3 + [ctypes.c_int, _I32P, _I32P, _I32P, ctypes.POINTER(tc_plan_info)]
+_lib.tc_suggest_layout.restype = ctypes.c_int
 _lib.tc_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p)] + _DESC * 3 + [ctypes.POINTER(tc_options)]
 _lib.tc_plan_create.restype = ctypes.c_int
 _lib.tc_plan_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(tc_plan_info)]
@@ -155,7 +157,7 @@ _lib.tc_status_string.restype = ctypes.c_char_p
 _lib.tc_last_error.restype = ctypes.c_char_p
 _lib.tc_version.restype = ctypes.c_char_p
 
-EXPORTED = ["tc_options_default", "tc_analyze", "tc_plan_create", "tc_plan_query", "tc_execute",
+EXPORTED = ["tc_options_default", "tc_analyze", "tc_suggest_layout", "tc_plan_create", "tc_plan_query", "tc_execute",
             "tc_plan_destroy", "tc_permute", "tc_batch_create", "tc_batch_workspace", "tc_batch_execute",
             "tc_batch_set_options", "tc_batch_query", "tc_batch_autotune", "tc_batch_destroy",
             "tc_picker_candidate", "tc_picker_features", "tc_picker_install", "tc_picker_uninstall",
@@ -234,6 +236,16 @@ def tc_analyze(dA, dB, dC, options=None):
     _check(_lib.tc_analyze(*dA.args(), *dB.args(), *dC.args(),
                            ctypes.byref(options) if options is not None else None, ctypes.byref(info)))
     return info
+
+
+def tc_suggest_layout(dA, dB, dC, fixed=0):
+    """Storage orders (one list of listed-mode indices per tensor, stride 1
+    first) and the analysis of the suggested layout; `fixed` as in the C ABI
+    (bit 0 A, bit 1 B, bit 2 C)."""
+    info = tc_plan_info()
+    orders = [(ctypes.c_int32 * max(1, d.rank))() for d in (dA, dB, dC)]
+    _check(_lib.tc_suggest_layout(*dA.args(), *dB.args(), *dC.args(), int(fixed), *orders, ctypes.byref(info)))
+    return [list(o)[:d.rank] for o, d in zip(orders, (dA, dB, dC))], info
 
 
 def tc_plan_create(dA, dB, dC, options=None):
@@ -409,6 +421,35 @@ def empty_colmajor(shape, device="cuda"):
         return torch.empty((), dtype=torch.float64, device=device)
     return torch.empty(list(reversed(shape)), dtype=torch.float64, device=device).permute(
         *reversed(range(len(shape))))
+
+
+def suggest_layout(labA, extA, labB, extB, labC, extC, fixed="", strides=None):
+    """The layout advice of the C ABI's tc_suggest_layout on label lists.
+
+    Returns ({"A": labels, "B": labels, "C": labels}, info): each tensor's
+    labels in the suggested storage order, stride-1 label first (strings when
+    the labels were given as strings).  `fixed` names the tensors kept as
+    given ("A", "BC", ...); `strides` optionally maps a fixed tensor's name to
+    its element strides (default: packed column-major in the listed order)."""
+    strides = strides or {}
+    specs = {"A": (labA, extA), "B": (labB, extB), "C": (labC, extC)}
+    descs = []
+    for name, (lab, ext) in specs.items():
+        ext = [int(e) for e in ext]
+        st = strides.get(name)
+        if st is None:
+            st, acc = [], 1
+            for e in ext:
+                st.append(acc)
+                acc *= max(e, 1)
+        descs.append(Desc(ext, st, lab))
+    mask = sum(1 << i for i, name in enumerate("ABC") if name in fixed.upper())
+    orders, info = tc_suggest_layout(*descs, fixed=mask)
+    out = {}
+    for (name, (lab, _)), order in zip(specs.items(), orders):
+        seq = [lab[i] for i in order]
+        out[name] = "".join(seq) if isinstance(lab, str) else seq
+    return out, info
 
 
 def contract(A, labA, B, labB, labC, C=None, alpha=1.0, beta=0.0, **plan_kw):

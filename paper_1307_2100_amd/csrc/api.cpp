@@ -604,6 +604,43 @@ tc_status tc_analyze(int ra, const int64_t* ea, const int64_t* sa, const int32_t
   return TC_OK;
 }
 
+tc_status tc_suggest_layout(int ra, const int64_t* ea, const int64_t* sa, const int32_t* la, int rb,
+                            const int64_t* eb, const int64_t* sb, const int32_t* lb, int rc, const int64_t* ec,
+                            const int64_t* sc, const int32_t* lc, int fixed, int32_t* order_a, int32_t* order_b,
+                            int32_t* order_c, tc_plan_info* info) {
+  if (fixed < 0 || fixed > 7) return fail(TC_ERR_INVALID_ARG, "fixed must be a mask of bits 0 (A), 1 (B), 2 (C)");
+  const int rank[3] = {ra, rb, rc};
+  const int64_t* ext[3] = {ea, eb, ec};
+  const int64_t* str[3] = {sa, sb, sc};
+  const int32_t* lab[3] = {la, lb, lc};
+  int32_t* ord[3] = {order_a, order_b, order_c};
+  const char* name[3] = {"A", "B", "C"};
+  tc::TensorDesc T[3];
+  for (int t = 0; t < 3; ++t) {
+    if (rank[t] > 0 && !ord[t]) return fail(TC_ERR_INVALID_ARG, std::string("null order array for ") + name[t]);
+    // without strides: packed column-major in the listed order
+    std::vector<int64_t> packed(rank[t] > 0 && rank[t] <= TC_MAX_RANK ? rank[t] : 0);
+    int64_t stride = 1;
+    for (size_t i = 0; i < packed.size() && ext[t]; ++i) {
+      packed[i] = stride;
+      stride *= ext[t][i] > 0 ? ext[t][i] : 1;
+    }
+    tc_status s = fill_desc(&T[t], rank[t], ext[t], str[t] ? str[t] : packed.data(), lab[t], name[t]);
+    if (s != TC_OK) return s;
+  }
+  int order[3][TC_MAX_RANK];
+  int* op[3] = {order[0], order[1], order[2]};
+  tc::TensorDesc suggested[3];
+  tc::Analysis an;
+  std::string err;
+  tc_status s = tc::suggest_layout(T[0], T[1], T[2], fixed, op, suggested, &an, &err);
+  if (s != TC_OK) return fail(s, err);
+  for (int t = 0; t < 3; ++t)
+    for (int j = 0; j < rank[t]; ++j) ord[t][j] = order[t][j];
+  if (info) *info = an.info;
+  return TC_OK;
+}
+
 tc_status tc_plan_create(tc_plan_t* out, int ra, const int64_t* ea, const int64_t* sa, const int32_t* la, int rb,
                          const int64_t* eb, const int64_t* sb, const int32_t* lb, int rc, const int64_t* ec,
                          const int64_t* sc, const int32_t* lc, const tc_options* opt) {

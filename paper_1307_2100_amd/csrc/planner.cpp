@@ -133,12 +133,17 @@ int64_t product(const TensorDesc& t) {
 // Rule picker for the GEMM tile: the largest tile (most wavefronts per
 // workgroup, most reuse per byte staged) that still gives each of the 256
 // compute units a workgroup; smaller tiles as the problem shrinks.
-int pick_tile(int64_t M, int64_t N, int64_t L) {
+int pick_tile(int64_t M, int64_t N, int64_t K, int64_t L) {
   auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * L; };
   if (tiles(256, 128) >= 256) return 11;
   if (tiles(128, 256) >= 256) return 12;
   if (tiles(128, 128) >= 256) return 9;
   if (tiles(64, 64) >= 256) return 1;
+  // Fewer output tiles than the chip has compute units, over a long
+  // contracted range: split-K makes up the workgroup count, but only below
+  // 128 tiles, so take a tile size that lands there (32 x 32 tiles at 128 or
+  // more would run one long k loop per tile on too few workgroups).
+  if (K >= 2048 && tiles(32, 32) >= 128) return tiles(64, 64) >= 128 ? 9 : 1;
   return 8;
 }
 
@@ -583,7 +588,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     an.kernel = Analysis::KERNEL_BATCHED;
     build_slabs(an);
   } else if (recipe == TC_RECIPE_GEMM || recipe == TC_RECIPE_COPY_GEMM) {
-    info.tile_id = opt.tile_id >= 0 ? opt.tile_id : pick_tile(info.M, info.N, info.L);
+    info.tile_id = opt.tile_id >= 0 ? opt.tile_id : pick_tile(info.M, info.N, info.K, info.L);
     // few output tiles over a long contracted range: cut the range into
     // segments so that more workgroups share the work (split-K)
     const TileCfg& t = kTiles[info.tile_id];
@@ -631,6 +636,91 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
   info.kernel = an.kernel;
   *out = an;
   return TC_OK;
+}
+
+// Layout advice (Sec. 3.3 and the closing remarks of Sec. 5): when the inputs
+// can be generated in any storage order and both have a free index, storing a
+// free index at stride 1 puts the contraction in Class 3.2, so GEMM applies
+// without a copy.  The suggestion stores A as [free-A, contracted, batch], B
+// as [contracted, free-B, batch] and C as [free-A, free-B, batch]: the
+// column-major GEMM C(M,N) = A(M,K) B(K,N) per batch index.  Each index group
+// keeps one order in every tensor that holds it (taken from a fixed tensor
+// when there is one), so each group fuses into a single mode.  When A is
+// fixed with a contracted (or batch) index at stride 1, B leads with its free
+// indices instead, which keeps the class at 3.2 when B has a free index.
+tc_status suggest_layout(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, int fixed,
+                         int* order[3], TensorDesc out_desc[3], Analysis* out, std::string* err) {
+  tc_options o;
+  tc_options_default(&o);
+  Analysis an;
+  tc_status s = analyze(A, B, C, o, &an, err);
+  if (s != TC_OK) return s;
+  const TensorDesc* T[3] = {&A, &B, &C};
+  // storage order of a tensor: its modes by ascending stride (ties: position)
+  auto storage = [](const TensorDesc& t) {
+    std::vector<int> idx(t.rank);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return t.str[a] < t.str[b]; });
+    return idx;
+  };
+  // the order a group's labels take from tensor t: its storage order when
+  // fixed, its listing order otherwise
+  auto source = [&](int t) {
+    if (fixed & (1 << t)) return storage(*T[t]);
+    std::vector<int> idx(T[t]->rank);
+    std::iota(idx.begin(), idx.end(), 0);
+    return idx;
+  };
+  // role of a label: 0 free-A, 1 free-B, 2 contracted, 3 batch
+  auto role = [&](int32_t l) {
+    const bool a = find_label(A, l) >= 0, b = find_label(B, l) >= 0, c = find_label(C, l) >= 0;
+    return a && b && c ? 3 : a && b ? 2 : a ? 0 : 1;
+  };
+  // group labels in the order of the first fixed tensor that holds the group
+  // (by preference), else of the first preferred tensor that holds it
+  const int prefs[4][3] = {{0, 2, -1}, {1, 2, -1}, {0, 1, -1}, {2, 0, 1}};
+  std::vector<int32_t> group[4];
+  for (int g = 0; g < 4; ++g) {
+    int src = -1;
+    for (int pass = 0; pass < 2 && src < 0; ++pass)
+      for (int q = 0; q < 3 && src < 0; ++q) {
+        const int t = prefs[g][q];
+        if (t < 0 || (pass == 0 && !(fixed & (1 << t)))) continue;
+        src = t;
+      }
+    for (int i : source(src))
+      if (role(T[src]->lab[i]) == g) group[g].push_back(T[src]->lab[i]);
+  }
+  // A fixed with a contracted or batch index at stride 1: B leads with free-B
+  bool b_free_first = false;
+  if (fixed & 1) {
+    const int ua = unit_mode(squeeze(A));
+    const TensorDesc sa = squeeze(A);
+    b_free_first = ua >= 0 && role(sa.lab[ua]) >= 2;
+  }
+  const int seq[3][3] = {{0, 2, 3}, {b_free_first ? 1 : 2, b_free_first ? 2 : 1, 3}, {0, 1, 3}};
+  for (int t = 0; t < 3; ++t) {
+    const TensorDesc& x = *T[t];
+    TensorDesc& d = out_desc[t];
+    d = x;
+    std::vector<int> ord;
+    if (fixed & (1 << t)) {
+      ord = storage(x);
+    } else {
+      for (int g : seq[t])
+        for (int32_t l : group[g]) {
+          const int i = find_label(x, l);
+          if (i >= 0) ord.push_back(i);
+        }
+      int64_t stride = 1;
+      for (int i : ord) {
+        d.str[i] = stride;
+        stride *= x.ext[i] > 0 ? x.ext[i] : 1;
+      }
+    }
+    for (int j = 0; j < x.rank; ++j) order[t][j] = ord[j];
+  }
+  return analyze(out_desc[0], out_desc[1], out_desc[2], o, out, err);
 }
 
 }  // namespace tc

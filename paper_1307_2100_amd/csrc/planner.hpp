@@ -101,6 +101,14 @@ struct Analysis {
 tc_status analyze(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, const tc_options& opt,
                   Analysis* out, std::string* err, bool allow_copy = true);
 
+// Storage orders that let the contraction run as one direct GEMM (the
+// paper's layout advice).  Bit t of `fixed` keeps tensor t (A, B, C) as
+// given.  order[t][j] receives the mode of tensor t stored j-th (j = 0 at
+// stride 1); out_desc[t] the tensor with packed column-major strides in that
+// order (a fixed tensor keeps its strides); *out the analysis of that layout.
+tc_status suggest_layout(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, int fixed,
+                         int* order[3], TensorDesc out_desc[3], Analysis* out, std::string* err);
+
 // Picker features of an analysis (TC_PICKER_FEATURES floats).
 void picker_features(const Analysis& an, const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, float* f);
 

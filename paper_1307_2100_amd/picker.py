@@ -317,6 +317,28 @@ def install(path=DEFAULT_MODEL):
     return True
 
 
+def rules_now(recs):
+    """The rules of the current library against timed records.  A record's
+    rules time is its measured rules plan (candidate RULES) while the rules
+    still take the candidate they took at collection; when they now take
+    another table candidate, that candidate's measured time."""
+    t_rule, best, changed = [], [], 0
+    for r in recs:
+        ms = np.array([np.nan if (v is None or v < 0) else v for v in r["ms"]], dtype=np.float64)
+        _, now = tc_picker_features(*_descs(r["shape"]))
+        t = ms[RULES]
+        if now != r["rule_candidate"] and now >= 0 and np.isfinite(ms[now]):
+            changed += 1
+            t = ms[now]
+        t_rule.append(t)
+        best.append(np.nanmin(ms))
+    t_rule, best = np.array(t_rule), np.array(best)
+    return {"shapes": len(recs), "rules_changed_since_collection": changed,
+            "geomean_rules_over_best": float(np.exp(np.mean(np.log(t_rule / best)))),
+            "within_5pct_rules": float(np.mean(t_rule <= 1.05 * best)),
+            "worst_rules_over_best": float(np.max(t_rule / best)), "total_ms_rules": float(t_rule.sum())}
+
+
 # ---------------------------------------------------------------------- CLI
 def _split(recs, n_test):
     """Held-out shapes: the last n_test records by index (disjoint seeds)."""
@@ -340,7 +362,14 @@ def main(argv=None):
     e = sub.add_parser("evaluate")
     e.add_argument("--data", nargs="+", required=True)
     e.add_argument("--model", default=DEFAULT_MODEL)
+    r = sub.add_parser("rules", help="host only: the current rules against timed data")
+    r.add_argument("--data", nargs="+", required=True)
+    r.add_argument("--test", type=int, default=5000)
     a = ap.parse_args(argv)
+    if a.cmd == "rules":
+        tr, te = _split(load_records(a.data), a.test)
+        print(json.dumps({"heldout": rules_now(te), "train": rules_now(tr)}), flush=True)
+        return
     if a.cmd == "collect":
         collect(a.out, a.n, a.seed)
     elif a.cmd == "train":

@@ -337,3 +337,19 @@ def test_fast_division_method():
         ns = [0, 1, d - 1, d, d + 1, (1 << 31) - 1, (1 << 31) - 2] + [int(x) for x in g.integers(0, 1 << 31, 50)]
         for n in ns:
             assert ((n * mul) >> 32) >> (p - 32) == n // d, (n, d)
+
+
+def test_long_contracted_range_tile_rule():
+    """Few output tiles over a long contracted range: the rules move from
+    32x32 tiles (no split-K at 128 tiles or more) to 64x64 or 128x128 tiles
+    that split the range."""
+    ext = {"a": 384, "k": 147456, "b": 384}
+    info = analyze("ak", "kb", "ab", ext)
+    assert info.tile_id == 1 and info.k_split > 1
+    ext = {"a": 777, "k": 2100, "b": 700}
+    info = analyze("ak", "kb", "ab", ext)
+    assert info.tile_id == 9 and info.k_split > 1
+    # short range or enough tiles: unchanged
+    assert analyze("ak", "kb", "ab", {"a": 383, "k": 1000, "b": 390}).tile_id == 8
+    assert analyze("ak", "kb", "ab", {"a": 100, "k": 100000, "b": 100}).tile_id == 8
+    assert analyze("ak", "kb", "ab", {"a": 4096, "k": 4096, "b": 4096}).tile_id == 11

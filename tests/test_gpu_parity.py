@@ -224,3 +224,44 @@ def test_grid_stride_over_huge_output_counts():
     s, _ = oracle.contract_entries(dA.cpu().numpy(), labA, dB.cpu().numpy(), labB, labC, idx)
     got = C.cpu().numpy()[tuple(idx.T)]
     assert np.array_equal(got, s)
+
+
+@pytest.mark.parametrize("case", ["class31", "cc_b", "xy_b", "class32", "3d_matrix"])
+def test_suggested_layout_runs_as_direct_gemm(case):
+    """Inputs re-stored in the orders tc_suggest_layout proposes plan as one
+    direct GEMM with no copy (Class 3.2) and give the oracle's result for the
+    original layout."""
+    _, la, lb, lc, ext = next(c for c in CASES if c[0] == case)
+    A, B = synth.make_operands(11, la, lb, ext, kind="uniform")
+    ref, absr = reference(A, la, B, lb, lc)
+    out, info = tc.suggest_layout(la, [ext[l] for l in la], lb, [ext[l] for l in lb], lc, [ext[l] for l in lc])
+    assert info.paper_class == 32 and info.recipe == tc.TC_RECIPE_GEMM and info.copy_operand == -1
+
+    def restored(X, lab, new):
+        return to_dev(np.asfortranarray(np.transpose(X, [lab.index(l) for l in new])))
+
+    dA, dB = restored(A, la, out["A"]), restored(B, lb, out["B"])
+    C = colmajor_zeros([ext[l] for l in out["C"]])
+    plan = tc.Plan.for_tensors(dA, out["A"], dB, out["B"], C, out["C"])
+    try:
+        assert plan.info.recipe == tc.TC_RECIPE_GEMM and plan.info.copy_operand == -1
+        plan.execute(dA, dB, C)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    got = np.transpose(C.cpu().numpy(), [out["C"].index(l) for l in lc])
+    err = componentwise_error(got, ref, absr)
+    print(case, out, "componentwise error %.3e" % err)
+    assert err <= FP64_TOL
+
+
+@pytest.mark.parametrize("ext,tile", [
+    ({"a": 383, "k": 2100, "b": 390}, 1),   # 32x32 tiles would be 156 with no split: 64x64 tiles + split-K
+    ({"a": 777, "k": 2100, "b": 700}, 9),   # 169 64x64 tiles: 128x128 tiles + split-K
+])
+def test_long_contracted_range_tiles_split(ext, tile):
+    labA, labB, labC = "ak", "kb", "ab"
+    A, B = synth.make_operands(15, labA, labB, ext, kind="integers")
+    got, info = _run(labA, labB, labC, A, B, "auto")
+    assert info["tile_id"] == tile and info["k_split"] > 1, info
+    assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
