@@ -68,12 +68,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_split_kernel(GettPara
                                            parts + (t * S + sg) * (int64_t)(BM * BN));
 }
 
+// Reduction of the split-K segments: workgroup (t, c) finishes entries
+// 256 c .. 256 c + 255 of tile t, one entry per thread.
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void gett_reduce_kernel(GettParams p, int64_t tilesM, int64_t tilesN, int S,
                                                           const double* __restrict__ parts) {
-  const int64_t t = blockIdx.x;
+  constexpr int CH = (BM * BN + 255) / 256;
+  const int64_t t = blockIdx.x / CH;
+  const int c = (int)(blockIdx.x % CH);
   const int64_t per = tilesM * tilesN, l = t / per, r = t % per;
-  gett_reduce_tile<BM, BN>(p, (r % tilesM) * BM, (r / tilesM) * BN, l, parts + t * S * (int64_t)(BM * BN), S);
+  gett_reduce_entry<BM, BN>(p, (r % tilesM) * BM, (r / tilesM) * BN, l, parts + t * S * (int64_t)(BM * BN), S,
+                            c * 256 + (int)threadIdx.x);
 }
 
 // The same GEMM for operands whose stride-1 mode leads their row group or
@@ -323,6 +328,7 @@ hipError_t launch_cfg(const GettParams& p, bool akf, bool bkf, int S, int64_t se
   if (total == 0) return hipSuccess;
   // a grid's total thread count must stay below 2^32
   if (total * S > 0xffffffffLL / (64 * WGM * WGN)) return hipErrorInvalidConfiguration;
+  if (S > 1 && total * ((BM * BN + 255) / 256) > 0xffffffffLL / 256) return hipErrorInvalidConfiguration;
   dim3 block(64 * WGM * WGN);
   if (S > 1) {
     dim3 grid((unsigned)(total * S));
@@ -336,8 +342,9 @@ hipError_t launch_cfg(const GettParams& p, bool akf, bool bkf, int S, int64_t se
 #undef TC_SPLIT_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((gett_reduce_kernel<BM, BN>), dim3((unsigned)total), dim3(256), 0, s, p, tilesM, tilesN, S,
-                       parts);
+    constexpr int CH = (BM * BN + 255) / 256;
+    hipLaunchKernelGGL((gett_reduce_kernel<BM, BN>), dim3((unsigned)(total * CH)), dim3(256), 0, s, p, tilesM,
+                       tilesN, S, parts);
     return hipGetLastError();
   }
   dim3 grid((unsigned)total);

@@ -276,4 +276,28 @@ TC_DEV void gett_reduce_tile(const GettParams& p, int64_t m0, int64_t n0, int64_
   }
 }
 
+// Entry e (row-major within the tile) of a split-K tile: the S segment sums
+// added in segment order, as in gett_reduce_tile, with the loads issued eight
+// at a time ahead of their (unchanged, in-order) additions.
+template <int BM, int BN>
+TC_DEV void gett_reduce_entry(const GettParams& p, int64_t m0, int64_t n0, int64_t l,
+                              const double* __restrict__ parts, int S, int e) {
+  const int64_t m = m0 + e / BN, n = n0 + e % BN;
+  if (e >= BM * BN || m >= p.M || n >= p.N) return;
+  double v = 0.0;
+  int sg = 0;
+  for (; sg + 8 <= S; sg += 8) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = parts[(int64_t)(sg + u) * BM * BN + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += x[u];
+  }
+  for (; sg < S; ++sg) v += parts[(int64_t)sg * BM * BN + e];
+  double* dst = p.C + off_at(p.cL, l) + off_at(p.cM, m) + off_at(p.cN, n);
+  v *= p.alpha;
+  if (p.beta != 0.0) v += p.beta * *dst;
+  *dst = v;
+}
+
 }  // namespace tc

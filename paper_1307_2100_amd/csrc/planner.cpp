@@ -135,6 +135,22 @@ int64_t product(const TensorDesc& t) {
 // compute units a workgroup; smaller tiles as the problem shrinks.
 int pick_tile(int64_t M, int64_t N, int64_t K, int64_t L) {
   auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * L; };
+  if (K >= 2048) {
+    // Long contracted range: 128 x 128 tiles (else 64 x 64) when they waste
+    // under a quarter of their area on padding and split-K (below 128 tiles)
+    // turns them into at least 256 workgroups.  Larger tiles would leave each
+    // segment too few k-steps; smaller ones stage too little per byte.
+    for (int id : {9, 1}) {
+      const TileCfg& t = kTiles[id];
+      const int64_t Mp = (M + t.bm - 1) / t.bm * t.bm, Np = (N + t.bn - 1) / t.bn * t.bn;
+      const int64_t n = tiles(t.bm, t.bn);
+      if (n >= 128 || 4 * M * N < 3 * Mp * Np) continue;
+      int split;
+      int64_t len;
+      choose_split(n, K, t.bk, &split, &len);
+      if (n * split >= 256) return id;
+    }
+  }
   if (tiles(256, 128) >= 256) return 11;
   if (tiles(128, 256) >= 256) return 12;
   if (tiles(128, 128) >= 256) return 9;

@@ -340,15 +340,16 @@ def test_fast_division_method():
 
 
 def test_long_contracted_range_tile_rule():
-    """Few output tiles over a long contracted range: the rules move from
-    32x32 tiles (no split-K at 128 tiles or more) to 64x64 or 128x128 tiles
-    that split the range."""
-    ext = {"a": 384, "k": 147456, "b": 384}
-    info = analyze("ak", "kb", "ab", ext)
-    assert info.tile_id == 1 and info.k_split > 1
-    ext = {"a": 777, "k": 2100, "b": 700}
-    info = analyze("ak", "kb", "ab", ext)
-    assert info.tile_id == 9 and info.k_split > 1
+    """Few output tiles over a long contracted range: the rules take 128x128
+    tiles, else 64x64, when padding wastes under a quarter of the tile and
+    split-K turns them into 256 or more workgroups; failing that they still
+    move from 32x32 tiles (no split-K at 128 tiles or more) to 64x64 or
+    128x128 tiles that split the range."""
+    for (m, k, n), tile in (((384, 147456, 384), 9), ((512, 262144, 512), 9), ((192, 36864, 192), 1),
+                            ((3600, 10 ** 6, 60), 1), ((2025, 10 ** 6, 45), 1), ((1000, 3000, 1000), 9),
+                            ((256, 10000, 256), 1), ((383, 2100, 390), 1), ((777, 2100, 700), 9)):
+        info = analyze("ak", "kb", "ab", {"a": m, "k": k, "b": n})
+        assert info.tile_id == tile and info.k_split > 1, (m, k, n, info.tile_id)
     # short range or enough tiles: unchanged
     assert analyze("ak", "kb", "ab", {"a": 383, "k": 1000, "b": 390}).tile_id == 8
     assert analyze("ak", "kb", "ab", {"a": 100, "k": 100000, "b": 100}).tile_id == 8

@@ -255,13 +255,19 @@ def test_suggested_layout_runs_as_direct_gemm(case):
     assert err <= FP64_TOL
 
 
-@pytest.mark.parametrize("ext,tile", [
-    ({"a": 383, "k": 2100, "b": 390}, 1),   # 32x32 tiles would be 156 with no split: 64x64 tiles + split-K
-    ({"a": 777, "k": 2100, "b": 700}, 9),   # 169 64x64 tiles: 128x128 tiles + split-K
+@pytest.mark.parametrize("ext,tile,forced", [
+    ({"a": 383, "k": 2100, "b": 390}, 1, False),   # the rules: 64x64 tiles + split-K
+    ({"a": 777, "k": 2100, "b": 700}, 9, False),   # the rules: 128x128 tiles + split-K
+    ({"a": 500, "k": 8192, "b": 510}, 11, True),   # split-K on the largest tiles, ragged edges
+    ({"a": 380, "k": 8192, "b": 380}, 12, True),
+    ({"a": 380, "k": 4096, "b": 380}, 5, True),
+    ({"a": 380, "k": 4096, "b": 380}, 2, True),
 ])
-def test_long_contracted_range_tiles_split(ext, tile):
+def test_long_contracted_range_tiles_split(ext, tile, forced):
+    """Split-K segments and their reduction (one entry per thread, segments
+    added in order) on each tile shape: bit-exact on integers."""
     labA, labB, labC = "ak", "kb", "ab"
     A, B = synth.make_operands(15, labA, labB, ext, kind="integers")
-    got, info = _run(labA, labB, labC, A, B, "auto")
+    got, info = _run(labA, labB, labC, A, B, "auto", tile_id=tile if forced else -1)
     assert info["tile_id"] == tile and info["k_split"] > 1, info
     assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
