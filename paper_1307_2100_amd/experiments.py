@@ -15,6 +15,9 @@ column-major in the listed label order):
            GER.
   gr       Sec. 4.2, example 2: the same contraction with i = j = 4 and long
            free extents.
+  slices   Sec. 2.4: the square contraction run as the paper's slice loops
+           (one library call per slice; GEMM, GEMV, GER and DOT slicings)
+           against the fused launch.
   layout   Sec. 3.3: a Class 3.1 layout timed as given and re-stored in the
            orders tc_suggest_layout returns (direct GEMM).
 
@@ -152,6 +155,64 @@ def run_layout(la, lb, lc, ext, seed):
     return rows
 
 
+def run_slicings(la, lb, lc, ext, slicings, seed):
+    """The fused launch against the paper's slice loops (one library call per
+    slice, Sec. 2.4) for each slicing in `slicings` (labels looped over)."""
+    from . import slicing
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    A, B = _uniform(_shape(la, ext), gen), _uniform(_shape(lb, ext), gen)
+    K = 1
+    for l in la:
+        if l in lb and l not in lc:
+            K *= ext[l]
+    flops = 2.0 * K
+    for l in set(la) | set(lb):
+        if not (l in la and l in lb and l not in lc):
+            flops *= ext[l]
+    ref = tc.empty_colmajor(_shape(lc, ext), device="cuda")
+    plan = tc.Plan.for_tensors(A, la, B, lb, ref, lc)
+    try:
+        ms, reps = _time(plan, A, B, ref)
+        ran = tc.RECIPE_NAMES[plan.info.recipe]
+    finally:
+        plan.close()
+    rows = [{"study": "slices", "contraction": "%s,%s->%s" % (la, lb, lc), "extents": {l: ext[l] for l in sorted(ext)},
+             "sliced": "", "calls": 1, "ran": ran, "ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 2),
+             "max_diff_over_K": 0.0}]
+    print(json.dumps(rows[0]), flush=True)
+    for sl in slicings:
+        C = tc.empty_colmajor(_shape(lc, ext), device="cuda")
+        slicing.run_sliced(A, la, B, lb, C, lc, sl)          # untimed first pass
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        calls = slicing.run_sliced(A, la, B, lb, C, lc, sl)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        diff = float((C - ref).abs().max()) / K
+        row = {"study": "slices", "contraction": "%s,%s->%s" % (la, lb, lc), "extents": {l: ext[l] for l in sorted(ext)},
+               "sliced": sl, "calls": calls, "ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 2),
+               "max_diff_over_K": diff}
+        print(json.dumps(row), flush=True)
+        if diff > 1e-12:
+            raise RuntimeError("slicing %s disagrees with the fused result: %.3e" % (sl, diff))
+        rows.append(row)
+        del C
+    del A, B, ref
+    torch.cuda.empty_cache()
+    return rows
+
+
+def slicing_workloads(quick):
+    # R[a,h] = A[a,b,g] B[h,b,g] (Sec. 4.1): slicing g leaves GEMMs; h and g,
+    # GEMVs; b and g, GERs; a and h, DOTs over (b, g)
+    for n in ((64, 128) if quick else (64, 128, 256)):
+        sl = ["g", "b"] + (["hg", "bg", "ah"] if n <= 128 else [])
+        yield "abg", "hbg", "ah", {l: n for l in "abgh"}, sl
+
+
 def workloads(quick):
     sq = (64, 128, 256) if quick else (64, 128, 192, 256, 384, 512)
     cc_ij = (500, 1000) if quick else (500, 1000, 2000)
@@ -215,6 +276,16 @@ def markdown(rows, cmd):
                 cells.append(txt)
             lines.append("| %s | %s | %s | %s |" % (k[0], extent_s, auto["paper_class"], " | ".join(cells)))
         lines.append("")
+    sel = [r for r in rows if r["study"] == "slices"]
+    if sel:
+        lines += ["## Sec. 2.4: the paper's slice loops (one library call per slice) against one fused launch", "",
+                  "| contraction | extents | labels looped over | calls | ms | GFLOP/s |", "|---|---|---|---|---|---|"]
+        for r in sel:
+            extent_s = " ".join("%s=%d" % (l, e) for l, e in r["extents"].items())
+            what = r["sliced"] or "none (fused, %s)" % r.get("ran", "")
+            lines.append("| %s | %s | %s | %d | %.3f | %s |" % (r["contraction"], extent_s, what, r["calls"], r["ms"],
+                                                             "%.0f" % r["gflops"] if r["gflops"] >= 10 else "%.2f" % r["gflops"]))
+        lines.append("")
     sel = [r for r in rows if r["study"] == "layout"]
     if sel:
         lines += ["## Sec. 3.3: layout advice (tc_suggest_layout)", "",
@@ -229,19 +300,23 @@ def markdown(rows, cmd):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--quick", action="store_true", help="smaller sizes (a few seconds)")
-    ap.add_argument("--study", action="append", choices=["square", "cc", "gr", "layout"],
+    ap.add_argument("--study", action="append", choices=["square", "cc", "gr", "slices", "layout"],
                     help="run only these studies (repeatable)")
     ap.add_argument("--md", help="write a markdown summary here")
     args = ap.parse_args(argv)
     assert torch.cuda.is_available(), "the experiments need a GPU"
     torch.cuda.set_device(0)
-    studies = set(args.study or ["square", "cc", "gr", "layout"])
+    studies = set(args.study or ["square", "cc", "gr", "slices", "layout"])
     rows = []
     t0 = time.time()
     for i, (study, la, lb, lc, ext) in enumerate(workloads(args.quick)):
         if study in studies:
             print("[experiments] %s %s,%s->%s %s" % (study, la, lb, lc, ext), file=sys.stderr, flush=True)
             rows += run_recipes(study, la, lb, lc, ext, RECIPES[study], 1307 * 1000 + i)
+    if "slices" in studies:
+        for i, (la, lb, lc, ext, sl) in enumerate(slicing_workloads(args.quick)):
+            print("[experiments] slices %s,%s->%s %s %s" % (la, lb, lc, ext, sl), file=sys.stderr, flush=True)
+            rows += run_slicings(la, lb, lc, ext, sl, 1307 * 3000 + i)
     if "layout" in studies:
         for i, (la, lb, lc, ext) in enumerate(layout_workloads(args.quick)):
             print("[experiments] layout %s,%s->%s %s" % (la, lb, lc, ext), file=sys.stderr, flush=True)
