@@ -94,7 +94,21 @@ void build_tables(const tc::Analysis& an, const OffsTargets& t, std::vector<int6
     }
     const int64_t n = g.size();
     pos.push_back({want[w].dst, host.size()});
-    for (int64_t i = 0; i < n; ++i) host.push_back(g.offset(want[w].slot, i));
+    // column-major walk of the group's multi-index with a running offset (no
+    // division per entry): the same values as g.offset(slot, i) for i < n
+    const int64_t* st = g.str[want[w].slot];
+    int64_t idx[TC_MAX_RANK] = {};
+    int64_t off = 0;
+    host.reserve(host.size() + (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+      host.push_back(off);
+      for (int d = 0; d < g.n; ++d) {
+        off += st[d];
+        if (++idx[d] < g.ext[d]) break;
+        off -= st[d] * g.ext[d];
+        idx[d] = 0;
+      }
+    }
   }
 }
 

@@ -18,6 +18,8 @@ column-major in the listed label order):
   slices   Sec. 2.4: the square contraction run as the paper's slice loops
            (one library call per slice; GEMM, GEMV, GER and DOT slicings)
            against the fused launch.
+  chain    Appendix: raising two indices of a rank-4 tensor with the metric,
+           in the least-flop pairwise order and in operand order.
   layout   Sec. 3.3: a Class 3.1 layout timed as given and re-stored in the
            orders tc_suggest_layout returns (direct GEMM).
 
@@ -205,6 +207,54 @@ def run_slicings(la, lb, lc, ext, slicings, seed):
     return rows
 
 
+def run_chain(n, seed):
+    """Raising two indices of a rank-4 tensor with the metric (the appendix):
+    R[e,f,c,d] = T[a,b,c,d] g[a,e] g[b,f], with the operands listed metric
+    first, evaluated in the least-flop order and in operand order (which
+    forms the outer product of the two metrics first)."""
+    from . import chain
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    T = _uniform([n] * 4, gen)
+    g = _uniform([n, n], gen)
+    ops = [(g, "ae"), (g, "bf"), (T, "abcd")]
+    rows, res = [], {}
+    ext = {ord(c): n for c in "abcdef"}
+    for order in ("optimal", "left"):
+        t0 = time.perf_counter()
+        ch = chain.Chain(ops, "efcd", order=order)
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        try:
+            tensors = [t for t, _ in ops]
+            stream = torch.cuda.current_stream()
+            ch.execute(tensors)                                # untimed first pass
+            torch.cuda.synchronize()
+            reps = 5
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                ch.execute(tensors)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            res[order] = ch.execute(tensors).clone()
+            torch.cuda.synchronize()
+        finally:
+            ch.close()
+        row = {"study": "chain", "contraction": "ae,bf,abcd->efcd", "extents": {"all": n}, "order": order,
+               "steps": len(ch.steps), "flops": ch.flops, "ms": round(ms, 4), "plan_ms": round(plan_ms, 3),
+               "gflops": round(ch.flops / ms / 1e6, 2)}
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    diff = float((res["optimal"] - res["left"]).abs().max()) / n ** 2
+    rows[-1]["max_diff_over_K"] = diff
+    if diff > 1e-12:
+        raise RuntimeError("chain orders disagree: %.3e" % diff)
+    del T, g, res
+    torch.cuda.empty_cache()
+    return rows
+
+
 def slicing_workloads(quick):
     # R[a,h] = A[a,b,g] B[h,b,g] (Sec. 4.1): slicing g leaves GEMMs; h and g,
     # GEMVs; b and g, GERs; a and h, DOTs over (b, g)
@@ -286,6 +336,17 @@ def markdown(rows, cmd):
             lines.append("| %s | %s | %s | %d | %.3f | %s |" % (r["contraction"], extent_s, what, r["calls"], r["ms"],
                                                              "%.0f" % r["gflops"] if r["gflops"] >= 10 else "%.2f" % r["gflops"]))
         lines.append("")
+    sel = [r for r in rows if r["study"] == "chain"]
+    if sel:
+        lines += ["## Appendix: raising two indices with the metric, R[e,f,c,d] = g[a,e] g[b,f] T[a,b,c,d]", "",
+                  "Planned once (order, intermediates, one plan per step), then timed over 5 executions with HIP "
+                  "events; planning time listed apart.", "",
+                  "| n (every extent) | order | steps | GFLOP | ms | GFLOP/s | planning ms |",
+                  "|---|---|---|---|---|---|---|"]
+        for r in sel:
+            lines.append("| %d | %s | %d | %.2f | %.3f | %.0f | %.2f |" % (
+                r["extents"]["all"], r["order"], r["steps"], r["flops"] / 1e9, r["ms"], r["gflops"], r["plan_ms"]))
+        lines.append("")
     sel = [r for r in rows if r["study"] == "layout"]
     if sel:
         lines += ["## Sec. 3.3: layout advice (tc_suggest_layout)", "",
@@ -300,13 +361,13 @@ def markdown(rows, cmd):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--quick", action="store_true", help="smaller sizes (a few seconds)")
-    ap.add_argument("--study", action="append", choices=["square", "cc", "gr", "slices", "layout"],
+    ap.add_argument("--study", action="append", choices=["square", "cc", "gr", "slices", "chain", "layout"],
                     help="run only these studies (repeatable)")
     ap.add_argument("--md", help="write a markdown summary here")
     args = ap.parse_args(argv)
     assert torch.cuda.is_available(), "the experiments need a GPU"
     torch.cuda.set_device(0)
-    studies = set(args.study or ["square", "cc", "gr", "slices", "layout"])
+    studies = set(args.study or ["square", "cc", "gr", "slices", "chain", "layout"])
     rows = []
     t0 = time.time()
     for i, (study, la, lb, lc, ext) in enumerate(workloads(args.quick)):
@@ -317,6 +378,10 @@ def main(argv=None):
         for i, (la, lb, lc, ext, sl) in enumerate(slicing_workloads(args.quick)):
             print("[experiments] slices %s,%s->%s %s %s" % (la, lb, lc, ext, sl), file=sys.stderr, flush=True)
             rows += run_slicings(la, lb, lc, ext, sl, 1307 * 3000 + i)
+    if "chain" in studies:
+        for i, n in enumerate((32, 64) if args.quick else (32, 64, 96)):
+            print("[experiments] chain n=%d" % n, file=sys.stderr, flush=True)
+            rows += run_chain(n, 1307 * 4000 + i)
     if "layout" in studies:
         for i, (la, lb, lc, ext) in enumerate(layout_workloads(args.quick)):
             print("[experiments] layout %s,%s->%s %s" % (la, lb, lc, ext), file=sys.stderr, flush=True)
