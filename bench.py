@@ -194,10 +194,11 @@ def main():
     if not args.no_split:
         split = split_runs(work, max(3, min(args.steps, 10)))
 
-    batch = memory = None
+    batch = memory = modes = None
     if not args.no_batch:
         batch = batch_runs()
         memory = memory_bound_runs()
+        modes = timing_modes_runs()
 
     precision_workload = None
     if args.precision_workload:
@@ -231,6 +232,7 @@ def main():
         "precision_workload": precision_workload,
         "batch_workload": batch,
         "memory_bound_kernels": memory,
+        "warm_cold_graph": modes,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -423,6 +425,87 @@ def batch_runs(n_random=2000, reps=10):
             "ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 1), "gb_s": round(nbytes / ms / 1e6, 1),
             "ideal_ms": round(ideal_ms, 4), "frac_roofline": round(ideal_ms / ms, 4),
             "max_componentwise_error_sampled": err, "grid_contractions_alone": gr}
+
+
+def timing_modes_runs(reps=10, graph_reps=20):
+    """The small 3-D contraction C[i,j,m] = A[i,k,m] B[k,j] (extents 64) and
+    the two grid contractions, each timed three ways with HIP events on the
+    current stream: warm (median of reps back-to-back-launched calls, each
+    bracketed by its own events), cold (a 1 GiB buffer is written before
+    each call, which evicts the 256 MB last-level cache; the call alone is
+    timed) and graph replay (the call captured once in a HIP graph, mean
+    over graph_reps replays).  Every replay's output is compared with the
+    eager result."""
+    import numpy as np
+    import torch
+
+    import paper_1307_2100_amd as tc
+    import synth
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1308)
+    stream = torch.cuda.current_stream()
+    scratch = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    out = {}
+    for name, (la, lb, lc, ext) in (("c0_3d_64", synth.workload_3d_matrix(64)), ("gr_r", synth.workload_gr_r()),
+                                    ("gr_s", synth.workload_gr_s())):
+        A = _dev_uniform(tc, torch, synth.shape_of(la, ext), gen)
+        B = _dev_uniform(tc, torch, synth.shape_of(lb, ext), gen)
+        C = tc.empty_colmajor(list(synth.shape_of(lc, ext)))
+        plan = tc.Plan.for_tensors(A, la, B, lb, C, lc)
+        ws = plan.workspace(C.device)
+        run = lambda: plan.execute(A, B, C, stream=stream, workspace=ws)  # noqa: E731
+        run()
+        torch.cuda.synchronize()
+        eager = C.clone()
+        warm, cold = [], []
+        for k in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            warm.append(e0.elapsed_time(e1))
+        for k in range(reps):
+            scratch.fill_(float(k))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            cold.append(e0.elapsed_time(e1))
+        # graph: captured on a side stream, replayed on the current one
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                plan.execute(A, B, C, stream=side, workspace=ws)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        mismatch = 0.0
+        for _ in range(3):
+            C.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            mismatch = max(mismatch, float((C - eager).abs().max()))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(graph_reps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        info = plan.info
+        out[name] = {"warm_ms_median": round(float(np.median(warm)), 4),
+                     "cold_ms_median": round(float(np.median(cold)), 4),
+                     "graph_replay_ms": round(e0.elapsed_time(e1) / graph_reps, 4),
+                     "graph_replay_max_abs_diff_vs_eager": mismatch,
+                     "kernel": tc.KERNEL_NAMES[info.kernel], "flops": info.flops, "bytes": info.bytes}
+        del g
+        plan.close()
+        del A, B, C, eager
+    del scratch
+    torch.cuda.empty_cache()
+    return out
 
 
 def memory_bound_runs(reps=20):

@@ -99,7 +99,6 @@ void build_tables(const tc::Analysis& an, const OffsTargets& t, std::vector<int6
     const int64_t* st = g.str[want[w].slot];
     int64_t idx[TC_MAX_RANK] = {};
     int64_t off = 0;
-    host.reserve(host.size() + (size_t)n);
     for (int64_t i = 0; i < n; ++i) {
       host.push_back(off);
       for (int d = 0; d < g.n; ++d) {
