@@ -495,6 +495,9 @@ def timing_modes_runs(reps=10, graph_reps=20):
         e1.record(stream)
         torch.cuda.synchronize()
         info = plan.info
+        print("[bench] %s: warm %.4f ms, cold %.4f ms, graph replay %.4f ms" % (
+            name, float(np.median(warm)), float(np.median(cold)), e0.elapsed_time(e1) / graph_reps),
+            file=sys.stderr, flush=True)
         out[name] = {"warm_ms_median": round(float(np.median(warm)), 4),
                      "cold_ms_median": round(float(np.median(cold)), 4),
                      "graph_replay_ms": round(e0.elapsed_time(e1) / graph_reps, 4),
