@@ -707,7 +707,7 @@ tc_status tc_plan_create(tc_plan_t* out, int ra, const int64_t* ea, const int64_
     p->slab.aL = p->aL;
     p->slab.bL = p->bL;
     p->slab.cL = p->cL;
-    s = fill_slab(p->an, p->slab, tc::kBatchedLdsDoubles, host, pos);
+    s = fill_slab(p->an, p->slab, tc::kBatchedSlabLdsDoubles, host, pos);
     if (s != TC_OK) {
       delete p;
       return s;

@@ -303,6 +303,11 @@ struct BatchedParams {
   double alpha, beta;
 };
 constexpr int kBatchedLdsDoubles = 2048;  // 16 KB of LDS per workgroup: several workgroups per CU
+// LDS budget of the standalone slab kernel's batch points per workgroup
+#ifndef TC_SLAB_LDS_DOUBLES
+#define TC_SLAB_LDS_DOUBLES 2048
+#endif
+constexpr int kBatchedSlabLdsDoubles = TC_SLAB_LDS_DOUBLES;
 // Points per workgroup for per-point slabs of `per` doubles and K contracted
 // indices (the contracted offsets of A and B are staged in LDS as well).
 inline int slab_points(int per, int K, int lds_doubles) {

@@ -214,7 +214,7 @@ void build_slabs(Analysis& an) {
     an.slab_s0[slot] = dense ? std::get<0>(modes[0]) : 0;
   }
   const int per = an.slab_size[0] + an.slab_size[1] + an.slab_size[2];
-  an.batched_P = slab_points(per, (int)K, kBatchedLdsDoubles);
+  an.batched_P = slab_points(per, (int)K, kBatchedSlabLdsDoubles);
   (void)M;
   (void)N;
 }
