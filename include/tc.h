@@ -152,10 +152,12 @@ tc_status tc_analyze(int rank_a, const int64_t* ext_a, const int64_t* str_a, con
  * tensor when there is one.  When both inputs have a free index, A or B is not
  * fixed and no fixed input has a batch index at stride 1, the suggested
  * layout is Class 3.2 and each index group of a free tensor is contiguous
- * (with nothing fixed, every group fuses into one mode).  info (may be NULL) receives
- * the analysis of the suggested layout with packed strides.  Errors: those of
- * tc_analyze; TC_ERR_INVALID_ARG for a null order array or fixed outside
- * 0..7.  Nothing is written to the order arrays on error. */
+ * (with nothing fixed, every group fuses into one mode).  info (may be NULL)
+ * receives the analysis of the suggested layout: free tensors packed
+ * column-major in their suggested order, fixed tensors with their own
+ * strides.  Errors: those of tc_analyze; TC_ERR_INVALID_ARG for a null order
+ * array or fixed outside 0..7.  Nothing is written to the order arrays on
+ * error. */
 tc_status tc_suggest_layout(int rank_a, const int64_t* ext_a, const int64_t* str_a, const int32_t* lab_a,
                             int rank_b, const int64_t* ext_b, const int64_t* str_b, const int32_t* lab_b,
                             int rank_c, const int64_t* ext_c, const int64_t* str_c, const int32_t* lab_c,
