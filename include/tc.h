@@ -53,7 +53,7 @@ typedef enum {
   TC_ERR_OUTPUT_OVERLAP = 4,   /* C's strides map two entries to one address */
   TC_ERR_RANK = 5,             /* rank < 0 or > TC_MAX_RANK */
   TC_ERR_WORKSPACE = 6,        /* workspace smaller than tc_plan_info.workspace_bytes */
-  TC_ERR_UNSUPPORTED = 7,      /* valid request this build does not implement */
+  TC_ERR_UNSUPPORTED = 7,      /* valid request the library does not implement */
   TC_ERR_HIP = 8,              /* a HIP runtime call failed (message in tc_last_error) */
   TC_ERR_NOMEM = 9             /* host or device allocation failed */
 } tc_status;
