@@ -39,13 +39,3 @@ def test_sliced_matches_oracle(la, lb, lc, ext, sl):
     want = 2.0 * oracle.contract(A, la, B, lb, lc) - C0
     assert np.array_equal(C.cpu().numpy(), want)
 
-
-def test_sliced_rejects_bad_slicings():
-    A = torch.zeros(3, 4, dtype=torch.float64)
-    B = torch.zeros(4, 5, dtype=torch.float64)
-    C = torch.zeros(3, 5, dtype=torch.float64)
-    with pytest.raises(ValueError):
-        slicing.run_sliced(A, "ak", B, "kb", C, "ab", "z")
-    with pytest.raises(ValueError):
-        slicing.run_sliced(A, "ak", B, "kb", C, "ab", "kk")
-    assert slicing.slice_count(A, "ak", B, "kb", "ab") == 15
