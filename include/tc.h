@@ -28,6 +28,13 @@
  *   - Errors are reported as tc_status codes only; tc_last_error() returns a
  *     thread-local message describing the last failure of the calling thread.
  *     A call that fails at validation writes nothing to C.
+ *   - Sizes: every count is a product of extents, formed with overflow-checked
+ *     multiplication.  Each tensor's element count and address span
+ *     (sum of (extent - 1) * stride) and the iteration space (product of the
+ *     extents of all distinct labels) must not exceed 2^56, else
+ *     TC_ERR_INVALID_ARG; a plan whose unfused index groups would need more
+ *     than 2^31 offset-table entries gets TC_ERR_UNSUPPORTED.  Host allocation
+ *     failures return TC_ERR_NOMEM; no C++ exception crosses the ABI.
  */
 #ifndef TC_H_
 #define TC_H_
@@ -175,19 +182,35 @@ tc_status tc_plan_create(tc_plan_t* out,
                          int rank_c, const int64_t* ext_c, const int64_t* str_c, const int32_t* lab_c,
                          const tc_options* opt);
 
-/* Copies the plan's description into *info. */
+/* Copies the plan's description into *info: the paper's class of the
+ * contraction (Sec. 3.2), the recipe taken (Sec. 3.2; the slicing it stands
+ * for, Sec. 2.4 and 3.1), the extents of the fused index groups and the
+ * algorithmic work, flops = 2 M N K L (Sec. 2.1's operation count of GEMM,
+ * carried over to the fused groups).  Errors: TC_ERR_INVALID_ARG for a null
+ * plan or info; nothing else. */
 tc_status tc_plan_query(tc_plan_t plan, tc_plan_info* info);
 
-/* Enqueues the contraction on `stream`.  A, B: device pointers to the first
- * element (index 0 in every mode) of each input; C: device pointer to the
- * output, read only when beta != 0 (BLAS convention).  workspace: device
- * memory of at least info.workspace_bytes bytes (may be NULL when that is
- * 0); it must not be used concurrently by another call.  A plan may run on
- * several streams at once with distinct workspaces. */
+/* Enqueues C <- alpha * sum A*B + beta * C (the contraction of Sec. 2.3, with
+ * alpha and beta as in the BLAS GEMM of Sec. 2.1) on `stream`.  A, B: device
+ * pointers to the first element (index 0 in every mode) of each input, laid
+ * out by the extents and strides the plan was built with; C: device pointer
+ * to the output, read only when beta != 0 (BLAS convention, so NaNs in C are
+ * harmless with beta = 0).  An empty contracted range gives C = beta * C; an
+ * empty output writes nothing.  workspace: device memory of at least
+ * info.workspace_bytes bytes (may be NULL when that is 0), caller-owned; it
+ * must not be used concurrently by another call.  A plan may run on several
+ * streams at once with distinct workspaces.  Errors (nothing is enqueued):
+ * TC_ERR_INVALID_ARG for a null plan, null A, B or C where they are read or
+ * written, or a current device other than the plan's; TC_ERR_WORKSPACE for a
+ * workspace below info.workspace_bytes; TC_ERR_HIP when a launch fails. */
 tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C,
                      double alpha, double beta, void* workspace, size_t workspace_bytes,
                      void* stream);
 
+/* Releases a plan from tc_plan_create and its device offset tables (Sec. 2.4:
+ * the slicing loops the tables stand for).  NULL is accepted (TC_OK).  The
+ * caller must make sure no enqueued tc_execute of the plan is still pending:
+ * the tables are freed at once. */
 tc_status tc_plan_destroy(tc_plan_t plan);
 
 /* Storage reordering (the copy of Sec. 3.1 F1 / the COPY of COPY+GEMM):

@@ -399,6 +399,14 @@ struct tc_batch_s {
 
   // Tiles and task list for one tile configuration, longest tasks first.
   tc_status set_config(int cfg) {
+    try {
+      return set_config_lists(cfg);
+    } catch (const std::bad_alloc&) {
+      return fail(TC_ERR_NOMEM, "host allocation of the batch task list failed");
+    }
+  }
+
+  tc_status set_config_lists(int cfg) {
     if (done_recorded) (void)hipEventSynchronize(done);
     drop_graph();
     const int BM = tc::kBatchTileBM[cfg], BN = tc::kBatchTileBN[cfg];
@@ -700,18 +708,22 @@ tc_status tc_plan_create(tc_plan_t* out, int ra, const int64_t* ea, const int64_
   }
   std::vector<int64_t> host;
   std::vector<std::pair<tc::Offs*, size_t>> pos;
-  build_tables(p->an, OffsTargets{&p->aM, &p->aK, &p->aL, &p->bN, &p->bK, &p->bL, &p->cM, &p->cN, &p->cL}, host,
-               pos);
   const bool slab = p->an.kernel == tc::Analysis::KERNEL_BATCHED;
-  if (slab) {
-    p->slab.aL = p->aL;
-    p->slab.bL = p->bL;
-    p->slab.cL = p->cL;
-    s = fill_slab(p->an, p->slab, tc::kBatchedSlabLdsDoubles, host, pos);
-    if (s != TC_OK) {
-      delete p;
-      return s;
+  try {
+    build_tables(p->an, OffsTargets{&p->aM, &p->aK, &p->aL, &p->bN, &p->bK, &p->bL, &p->cM, &p->cN, &p->cL}, host,
+                 pos);
+    if (slab) {
+      p->slab.aL = p->aL;
+      p->slab.bL = p->bL;
+      p->slab.cL = p->cL;
+      s = fill_slab(p->an, p->slab, tc::kBatchedSlabLdsDoubles, host, pos);
     }
+  } catch (const std::bad_alloc&) {
+    s = fail(TC_ERR_NOMEM, "host allocation of offset tables failed");
+  }
+  if (s != TC_OK) {
+    delete p;
+    return s;
   }
   s = upload_tables(host, pos, &p->d_tables);
   if (s != TC_OK) {
@@ -886,14 +898,26 @@ tc_status tc_permute(int rank, const int64_t* ext, const int64_t* str_x, const i
   if (rank > 0 && (!ext || !str_x || !str_y)) return fail(TC_ERR_INVALID_ARG, "null extent or stride array");
   tc::TensorDesc y;
   y.rank = rank;
-  int64_t total = 1;
+  bool empty = false;
   for (int i = 0; i < rank; ++i) {
     if (ext[i] < 0 || str_x[i] < 0 || str_y[i] < 0) return fail(TC_ERR_INVALID_ARG, "negative extent or stride");
     y.ext[i] = ext[i];
     y.str[i] = str_y[i];
-    total *= ext[i];
+    empty = empty || ext[i] == 0;
   }
-  if (total == 0) return TC_OK;
+  if (empty) return TC_OK;
+  {
+    // element count and both address spans within 2^56 (checked products)
+    const int64_t cap = (int64_t)1 << 56;
+    int64_t total = 1, span_x = 0, span_y = 0, r = 0;
+    for (int i = 0; i < rank; ++i) {
+      bool ok = !__builtin_mul_overflow(total, ext[i], &total) && total <= cap;
+      ok = ok && !__builtin_mul_overflow(ext[i] - 1, str_x[i], &r) && !__builtin_add_overflow(span_x, r, &span_x);
+      ok = ok && !__builtin_mul_overflow(ext[i] - 1, str_y[i], &r) && !__builtin_add_overflow(span_y, r, &span_y);
+      if (!ok || span_x > cap || span_y > cap)
+        return fail(TC_ERR_INVALID_ARG, "element count or address span exceeds 2^56");
+    }
+  }
   if (!X || !Y) return fail(TC_ERR_INVALID_ARG, "null X or Y");
   // reuse the output-overlap test of the planner through a trivial analysis
   {
@@ -942,10 +966,15 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
   }
   b->num_cus = prop.multiProcessorCount;
   if (prop.maxSharedMemoryPerMultiProcessor > 0) b->lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
-  b->items.resize(n);
-  b->analyses.resize(n);
   std::vector<int64_t> host;
   std::vector<std::pair<tc::Offs*, size_t>> pos;
+  try {
+    b->items.resize(n);
+    b->analyses.resize(n);
+  } catch (const std::bad_alloc&) {
+    delete b;
+    return fail(TC_ERR_NOMEM, "host allocation of batch items failed");
+  }
   for (int i = 0; i < n; ++i) {
     const tc_plan_s* p = plans[i];
     if (!p) {
@@ -982,24 +1011,31 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
     tc::BatchItem& it = b->items[i];
     std::memset(&it, 0, sizeof(it));
     it.swapped = an.info.swapped;
+    try {
+      if (an.kernel == tc::Analysis::KERNEL_BATCHED) {
+        build_tables(an, OffsTargets{&it.g.aM, &it.g.aK, &it.b.aL, &it.g.bN, &it.g.bK, &it.b.bL, &it.g.cM, &it.g.cN,
+                                     &it.b.cL},
+                     host, pos);
+        s = fill_slab(an, it.b, tc::kBatchSlabLdsDoubles, host, pos);
+      } else {
+        build_tables(an, OffsTargets{&it.g.aM, &it.g.aK, &it.g.aL, &it.g.bN, &it.g.bK, &it.g.bL, &it.g.cM, &it.g.cN,
+                                     &it.g.cL},
+                     host, pos);
+      }
+    } catch (const std::bad_alloc&) {
+      s = fail(TC_ERR_NOMEM, "host allocation of offset tables failed");
+    }
+    if (s != TC_OK) {
+      delete b;
+      return s;
+    }
     if (an.kernel == tc::Analysis::KERNEL_BATCHED) {
       it.kind = 1;
-      build_tables(an, OffsTargets{&it.g.aM, &it.g.aK, &it.b.aL, &it.g.bN, &it.g.bK, &it.b.bL, &it.g.cM, &it.g.cN,
-                                   &it.b.cL},
-                   host, pos);
-      s = fill_slab(an, it.b, tc::kBatchSlabLdsDoubles, host, pos);
-      if (s != TC_OK) {
-        delete b;
-        return s;
-      }
     } else {
       it.kind = an.kernel == tc::Analysis::KERNEL_LANES_K     ? tc::kBatchLanesK
                 : an.kernel == tc::Analysis::KERNEL_LANES_OUT ? tc::kBatchLanesOut
                                                               : tc::kBatchGemm;
       it.n_fastest = an.n_fastest ? 1 : 0;
-      build_tables(an, OffsTargets{&it.g.aM, &it.g.aK, &it.g.aL, &it.g.bN, &it.g.bK, &it.g.bL, &it.g.cM, &it.g.cN,
-                                   &it.g.cL},
-                   host, pos);
       it.akf = an.a_kfast ? 1 : 0;
       it.bkf = an.b_kfast ? 1 : 0;
       it.g.M = an.empty_out ? 0 : an.info.M;

@@ -24,6 +24,7 @@
 #include <vector>
 #include <climits>
 #include <cmath>
+#include <initializer_list>
 
 namespace tc {
 namespace {
@@ -128,6 +129,66 @@ int64_t product(const TensorDesc& t) {
   int64_t p = 1;
   for (int i = 0; i < t.rank; ++i) p *= t.ext[i];
   return p;
+}
+
+// Every size the planner derives is a product of extents.  analyze() first
+// checks, with overflow-checked multiplication, that each tensor's element
+// count and address span and the contraction's whole iteration space stay at
+// or below kMaxCount; after that the products it forms from subsets of the
+// extents cannot wrap, and the byte and padded-tile sizes built on them are
+// checked again where they are formed.
+constexpr int64_t kMaxCount = (int64_t)1 << 56;
+// Host offset tables (int64 entries, one per index of an unfused group) are
+// built and uploaded at plan time: at most this many entries per plan.
+constexpr int64_t kMaxTableEntries = (int64_t)1 << 31;
+
+bool mul_capped(int64_t a, int64_t b, int64_t* r) { return !__builtin_mul_overflow(a, b, r) && *r <= kMaxCount; }
+
+// a byte count sum of products: off += f0 * f1 * ... (false on overflow)
+bool add_product(size_t* off, std::initializer_list<int64_t> f) {
+  uint64_t v = 1;
+  for (int64_t x : f) {
+    if (x < 0 || __builtin_mul_overflow(v, (uint64_t)x, &v)) return false;
+  }
+  return !__builtin_add_overflow((uint64_t)*off, v, (uint64_t*)off) && *off <= ((uint64_t)1 << 62);
+}
+
+// Element count and address span of each tensor, and the iteration space
+// (product of the extents of all distinct labels), within kMaxCount.
+bool sizes_fit(const TensorDesc* const T[3], std::string* err) {
+  const char* name[3] = {"A", "B", "C"};
+  bool empty = false;
+  for (int s = 0; s < 3; ++s)
+    for (int i = 0; i < T[s]->rank; ++i) empty = empty || T[s]->ext[i] == 0;
+  for (int s = 0; s < 3; ++s) {
+    const TensorDesc& t = *T[s];
+    int64_t elems = 1, span = 0;
+    for (int i = 0; i < t.rank; ++i) {
+      if (t.ext[i] == 0) continue;
+      int64_t reach = 0;
+      if (!mul_capped(t.ext[i] - 1, t.str[i], &reach) || __builtin_add_overflow(span, reach, &span) ||
+          span > kMaxCount) {
+        *err = std::string("address span of ") + name[s] + " exceeds 2^56 elements";
+        return false;
+      }
+      if (!empty && !mul_capped(elems, t.ext[i], &elems)) {
+        *err = std::string("element count of ") + name[s] + " exceeds 2^56";
+        return false;
+      }
+    }
+  }
+  if (empty) return true;
+  int64_t space = 1;
+  for (int s = 0; s < 3; ++s)
+    for (int i = 0; i < T[s]->rank; ++i) {
+      bool seen = false;
+      for (int u = 0; u < s && !seen; ++u) seen = find_label(*T[u], T[s]->lab[i]) >= 0;
+      if (!seen && !mul_capped(space, T[s]->ext[i], &space)) {
+        *err = "iteration space (product of all distinct extents) exceeds 2^56";
+        return false;
+      }
+    }
+  return true;
 }
 
 // Rule picker for the GEMM tile: the largest tile (most wavefronts per
@@ -350,6 +411,7 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
       }
     }
   }
+  if (!sizes_fit(T, err)) return TC_ERR_INVALID_ARG;
   if (output_overlaps(C0)) {
     *err = "output strides overlap (two entries of C would share an address)";
     return TC_ERR_OUTPUT_OVERLAP;
@@ -529,6 +591,18 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
                 pairs(SA, GM, a_mfast, an.a_kfast) && pairs(SB, GN, b_nfast, an.b_kfast);
   }
 
+  {
+    // offset tables: one per (group of two or more modes, tensor holding it)
+    int64_t entries = 0;
+    const int holders[4] = {2, 2, 2, 3};
+    for (int gi = 0; gi < 4; ++gi)
+      if (G[gi].n > 1 && !an.empty_out) entries += holders[gi] * G[gi].size();
+    if (entries > kMaxTableEntries) {
+      *err = fmt("index groups that do not fuse need %lld offset-table entries (at most %lld)", entries,
+                 kMaxTableEntries);
+      return TC_ERR_UNSUPPORTED;
+    }
+  }
   info.M = G[GM].size();
   info.N = G[GN].size();
   info.K = G[GK].size();
@@ -583,25 +657,30 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     an.Mp = up(info.M, t.bm);
     an.Np = up(info.N, t.bn);
     an.Kp = up(info.K, fp8 ? 128 : t.bk);
-    const size_t esz = fp8 || crt ? 1 : 2;
+    const int64_t esz = fp8 || crt ? 1 : 2;
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-    size_t off = 0;
-    an.planesA_off = off;
-    off = al(off + (size_t)S * an.Mp * an.Kp * esz);
-    an.planesB_off = off;
-    off = al(off + (size_t)S * an.Np * an.Kp * esz);
-    an.zres_off = off;
-    if (crt) off = al(off + (size_t)S * an.Mp * an.Np);
-    an.sigA_off = off;
-    off = al(off + (size_t)an.Mp * sizeof(double));
-    an.sigB_off = off;
-    off = al(off + (size_t)an.Np * sizeof(double));
-    an.part_off = off;
     // scratch of the row-maximum pass, used by each input in turn
     const int64_t needA = row_max_segments(info.M, info.K) * info.M;
     const int64_t needB = row_max_segments(info.N, info.K) * info.N;
-    off = al(off + (size_t)(needA > needB ? needA : needB) * sizeof(double));
-    info.workspace_bytes = off;
+    size_t off = 0;
+    bool ok = true;
+    an.planesA_off = off;
+    ok = ok && add_product(&off, {S, an.Mp, an.Kp, esz});
+    an.planesB_off = off = al(off);
+    ok = ok && add_product(&off, {S, an.Np, an.Kp, esz});
+    an.zres_off = off = al(off);
+    if (crt) ok = ok && add_product(&off, {S, an.Mp, an.Np});
+    an.sigA_off = off = al(off);
+    ok = ok && add_product(&off, {an.Mp, (int64_t)sizeof(double)});
+    an.sigB_off = off = al(off);
+    ok = ok && add_product(&off, {an.Np, (int64_t)sizeof(double)});
+    an.part_off = off = al(off);
+    ok = ok && add_product(&off, {needA > needB ? needA : needB, (int64_t)sizeof(double)});
+    if (!ok) {
+      *err = "split-precision workspace size overflows";
+      return TC_ERR_INVALID_ARG;
+    }
+    info.workspace_bytes = al(off);
   } else if (opt.recipe == TC_RECIPE_AUTO && batched_fits(info, G)) {
     // Many tiny contractions sharing one layout (the batch group dominates):
     // per-point slabs through LDS, all batch indices in one launch.
@@ -620,7 +699,12 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     an.seg_len = len;
     if (split > 1) {
       an.part_offset = (info.workspace_bytes + 255) / 256 * 256;
-      info.workspace_bytes = an.part_offset + (size_t)tiles * split * t.bm * t.bn * sizeof(double);
+      size_t ws = an.part_offset;
+      if (!add_product(&ws, {tiles, split, t.bm, t.bn, (int64_t)sizeof(double)})) {
+        *err = "split-K workspace size overflows";
+        return TC_ERR_INVALID_ARG;
+      }
+      info.workspace_bytes = ws;
     }
     an.dma_ok = an.dma_ok && recipe == TC_RECIPE_GEMM && split == 1 && info.tile_id == kDmaTile;
     info.copy_fed = an.dma_ok ? 1 : 0;
@@ -649,7 +733,12 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
       an.seg = lanes_k ? k_segments(outputs, info.K) : out_segments(outputs, info.K);
       if (an.seg > 1) {
         an.part_offset = (info.workspace_bytes + 255) / 256 * 256;
-        info.workspace_bytes = an.part_offset + (size_t)(outputs * an.seg) * sizeof(double);
+        size_t ws = an.part_offset;
+        if (!add_product(&ws, {outputs, an.seg, (int64_t)sizeof(double)})) {
+          *err = "partial-sum workspace size overflows";
+          return TC_ERR_INVALID_ARG;
+        }
+        info.workspace_bytes = ws;
       }
     }
   }

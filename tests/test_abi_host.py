@@ -356,3 +356,88 @@ def test_long_contracted_range_tile_rule():
     assert analyze("ak", "kb", "ab", {"a": 383, "k": 1000, "b": 390}).tile_id == 8
     assert analyze("ak", "kb", "ab", {"a": 100, "k": 100000, "b": 100}).tile_id == 8
     assert analyze("ak", "kb", "ab", {"a": 4096, "k": 4096, "b": 4096}).tile_id == 11
+
+
+# ------------------------------------------------------------------ sizes
+# Every size the planner forms is a product of extents.  Layouts whose element
+# counts, address spans or iteration space pass 2^56 are rejected with a
+# status code before any product can wrap (zero strides make such extents
+# reachable without the memory to hold them).
+BIG = 1 << 20
+
+
+def _status_of(fn):
+    with pytest.raises(tc.TCError) as e:
+        fn()
+    return e.value.status
+
+
+def test_overflowing_extent_products_are_rejected_not_wrapped():
+    # four modes of 2^20 with strides 1, 2^20, 2^40, 2^60: the element count is 2^80
+    huge = tc.Desc([BIG] * 4, [1, BIG, 1 << 40, 1 << 60], "abcd")
+    B = tc.Desc([BIG] * 4, [1, BIG, 1 << 40, 1 << 60], "cdef")
+    C = tc.Desc([BIG] * 4, [1, BIG, 1 << 40, 1 << 60], "abef")
+    st = _status_of(lambda: tc.tc_analyze(huge, B, C))
+    assert st == tc.TC_ERR_INVALID_ARG
+    assert "2^56" in tc.tc_last_error()
+    # the same extents as a full contraction to a scalar: K = 2^80 used to wrap to 0
+    B2 = tc.Desc([BIG] * 4, [1, BIG, 1 << 40, 1 << 60], "abcd")
+    st = _status_of(lambda: tc.tc_analyze(huge, B2, tc.Desc([], [], "")))
+    assert st == tc.TC_ERR_INVALID_ARG
+
+
+def test_zero_stride_inputs_with_a_huge_iteration_space_are_rejected():
+    # broadcast inputs (stride 0 along k) of 2^48 entries each, and an output
+    # of 2^40: each tensor fits, but the contraction has 2^68 terms
+    A = tc.Desc([1 << 28, 1 << 20], [0, 1], "ki")
+    B = tc.Desc([1 << 28, 1 << 20], [0, 1], "kj")
+    C = tc.Desc([1 << 20, 1 << 20], [1, 1 << 20], "ij")
+    st = _status_of(lambda: tc.tc_analyze(A, B, C))
+    assert st == tc.TC_ERR_INVALID_ARG
+    assert "iteration space" in tc.tc_last_error()
+
+
+def test_address_span_overflow_is_rejected():
+    # 3 entries 2^62 apart: the span, not the count, leaves int64
+    A = tc.Desc([3, 2], [1 << 62, 1], "ka")
+    B = tc.Desc([3], [1], "k")
+    C = tc.Desc([2], [1], "a")
+    assert _status_of(lambda: tc.tc_analyze(A, B, C)) == tc.TC_ERR_INVALID_ARG
+    assert "span" in tc.tc_last_error()
+
+
+def test_sizes_at_the_limit_still_plan():
+    # iteration space exactly 2^56 through broadcast (stride-0) inputs, no overflow anywhere
+    A = tc.Desc([1 << 28, 1 << 14], [0, 1], "ki")
+    B = tc.Desc([1 << 28, 1 << 14], [0, 1], "kj")
+    C = tc.Desc([1 << 14, 1 << 14], [1, 1 << 14], "ij")
+    info = tc.tc_analyze(A, B, C)
+    assert (info.M, info.N, info.K) == (1 << 14, 1 << 14, 1 << 28)
+    assert info.flops == 2.0 * 2 ** 56
+    # one factor of two more is rejected
+    A2 = tc.Desc([1 << 29, 1 << 14], [0, 1], "ki")
+    B2 = tc.Desc([1 << 29, 1 << 14], [0, 1], "kj")
+    assert _status_of(lambda: tc.tc_analyze(A2, B2, C)) == tc.TC_ERR_INVALID_ARG
+    # the split-precision workspace of a near-limit plan is a checked sum, not a wrapped one
+    for prec in ("split_bf16", "split_fp8", "crt_int8"):
+        try:
+            info = tc.tc_analyze(A, B, C, tc.make_options(precision=prec))
+            assert info.workspace_bytes > 2 * (1 << 42)   # the planes hold every input digit
+        except tc.TCError as e:
+            assert e.status in (tc.TC_ERR_INVALID_ARG, tc.TC_ERR_UNSUPPORTED)
+
+
+def test_unfusable_groups_beyond_the_table_cap_are_unsupported():
+    # a two-mode free group that does not fuse (C stores it transposed) needs
+    # one offset-table entry per index; 2^32 entries exceed the cap
+    A = tc.Desc([1 << 16, 1 << 16, 2], [1, 0, 0], "abk")
+    B = tc.Desc([2, 3], [1, 2], "kj")
+    C = tc.Desc([1 << 16, 1 << 16, 3], [1 << 16, 1, 1 << 32], "abj")
+    assert _status_of(lambda: tc.tc_analyze(A, B, C)) == tc.TC_ERR_UNSUPPORTED
+    assert "offset-table" in tc.tc_last_error()
+
+
+def test_permute_rejects_overflowing_sizes_without_gpu():
+    st = _status_of(lambda: tc.tc_permute([BIG] * 4, [1, BIG, 1 << 40, 1 << 60], [1, BIG, 1 << 40, 1 << 60],
+                                          None, None, None))
+    assert st == tc.TC_ERR_INVALID_ARG
