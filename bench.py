@@ -1,23 +1,30 @@
-"""Benchmark: FP64 contraction throughput on the coupled-cluster workload.
+"""Benchmark: FP64 and split-precision contraction throughput on the
+coupled-cluster precision workload.
 
 One step = one pass of the hot path over one batch of input: the two
-coupled-cluster contractions at v = 128, o = 32,
+coupled-cluster contractions of the paper's Sec. 4.2 at v = 192, o = 48,
   (a) C[a,b,i,j] = sum_{c,d} A[a,b,c,d] B[c,d,i,j]   (paper class 3.2, direct GEMM)
   (b) C[a,b,i,j] = sum_{k,c} A[a,k,i,c] B[k,b,c,j]   (class 3.2 with un-fusable index groups)
-each through tc_execute on plans built once.  Inputs are seeded synthetic
-FP64 tensors (uniform in [-1, 1], column-major) resident in HBM before the
-timed region.  Prints one JSON line.
+each through tc_execute on plans built once, in FP64 (the headline value).
+Inputs are seeded synthetic FP64 tensors, N(0,1) with every slice along the
+last mode scaled by 10^U(-3,3), column-major, resident in HBM before the timed
+region.  The same step runs as split BF16 digits (the compared form), split
+FP8 digits and INT8 residues, each timed and each result's error stated
+against the compensated oracle on a stratified sample of outputs (one row
+per 128-row block times one column per 10-column block, about 66k entries,
+plus two full output slabs).  Prints one JSON line.
 
-Besides the step, the JSON line carries (outside the timed region) the
-split-precision runs on the same inputs, the batch workload (general-
-relativity grid contractions plus 2000 random contractions in one persistent
-graph-replayed launch), the memory-bound kernels' HBM rates, and the oracle
-timed on the host.
+Besides the step, the JSON line carries the same contractions at v = 128,
+o = 32 (uniform inputs), the batch workload (general-relativity grid
+contractions plus 2000 random contractions in one persistent graph-replayed
+launch), the memory-bound kernels' HBM rates, and the oracle timed on the
+host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-split] [--no-batch]
-                       [--precision-workload]
+                       [--no-c1] [--profile PRECISION]
 """
 import argparse
+import concurrent.futures
 import hashlib
 import json
 import os
@@ -30,6 +37,7 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0
 HBM_PEAK_GBS = 8000.0
+PRECISIONS = ("f64", "split_bf16", "split_fp8", "crt_int8")
 
 
 def parse():
@@ -37,20 +45,22 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--v", type=int, default=128)
-    ap.add_argument("--o", type=int, default=32)
+    ap.add_argument("--v", type=int, default=192)
+    ap.add_argument("--o", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU sample")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch workload and memory-bound kernels")
+    ap.add_argument("--no-c1", action="store_true", help="skip the v=128, o=32 workload")
+    ap.add_argument("--profile", choices=PRECISIONS, default=None,
+                    help="only build the workload and run the timed steps in this precision (for profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for hardware byte counters)")
-    ap.add_argument("--precision-workload", action="store_true",
-                    help="also run the precision workload (v=192, o=48, N(0,1)*10^U(-3,3) inputs)")
     return ap.parse_args()
 
 
 GETT_SOURCES = [os.path.join(ROOT, "paper_1307_2100_amd", "csrc", f) for f in ("gett_f64.hip", "gett_tile.hpp")]
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_gett_f64_dma_cc_a_v192_o48.json")
 
 
 def sha_of(paths):
@@ -61,16 +71,132 @@ def sha_of(paths):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_srcs):
+def traffic_from_profile(kernel_srcs, workload):
     """HBM traffic of the dominant kernel from committed counter runs, valid
-    only while the kernel source is unchanged since they were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_gett_f64_cc_a.json")
-    if not os.path.exists(path):
+    only while the kernel source is unchanged since they were taken and for
+    the workload they were taken on."""
+    if not os.path.exists(TRAFFIC_RECORD):
         return None
-    rec = json.load(open(path))
-    if rec.get("kernel_source_sha") != sha_of(kernel_srcs):
+    rec = json.load(open(TRAFFIC_RECORD))
+    if rec.get("kernel_source_sha") != sha_of(kernel_srcs) or rec.get("workload") != workload:
         return None
     return rec.get("bytes_per_launch")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def reference_entries(A, labA, B, labB, labC, idx):
+    """Compensated oracle sums and |A||B| sums of the sampled entries."""
+    import oracle
+    return oracle.contract_entries(A, labA, B, labB, labC, idx)
+
+
+def sample_indices(shape, seed):
+    """Stratified grid over C (rows: the first two modes, columns: the rest;
+    one row per block of 128, one column per block of 10), then two full
+    slabs C[a0, b0, :, :] of the last two modes."""
+    import numpy as np
+
+    import synth
+    grid = synth.stratified_entries(shape, 2, 128, 10, seed)
+    g = np.random.default_rng(seed + 1)
+    slabs = []
+    for _ in range(2):
+        r = [int(g.integers(0, e)) for e in shape[:2]]
+        cols = synth.unravel_colmajor(np.arange(int(np.prod(shape[2:]))), shape[2:])
+        slabs.append(np.concatenate([np.tile(np.array(r, dtype=np.int64), (cols.shape[0], 1)), cols], axis=1))
+    return np.concatenate([grid] + slabs, axis=0)
+
+
+def gather(C, idx):
+    """Entries of a dense (column-major) device tensor at the sampled
+    multi-indices, as host FP64."""
+    import numpy as np
+    import torch
+    off = np.zeros(idx.shape[0], dtype=np.int64)
+    span = 1
+    for d, (e, st) in enumerate(zip(C.shape, C.stride())):
+        off += idx[:, d] * st
+        span += (e - 1) * st
+    assert span == C.numel(), "gather expects a dense output tensor"
+    flat = torch.as_strided(C, (C.numel(),), (1,))
+    return flat.index_select(0, torch.from_numpy(off).to(C.device)).cpu().numpy()
+
+
+def errors(got, ref):
+    """(max componentwise error, normwise error) of sampled entries against the
+    compensated oracle: |got - s| / (|A||B|) per entry and max|got - s| / max|s|."""
+    import numpy as np
+    s, a = ref
+    comp = float(np.max(np.abs(got - s) / np.where(a > 0, a, 1.0)))
+    norm = float(np.max(np.abs(got - s)) / max(float(np.max(np.abs(s))), 1e-300))
+    return comp, norm
+
+
+def build_workload(tc, torch, synth, v, o, kind, wid_a, wid_b, dev):
+    work = {}
+    for name, spec, wid in (("cc_a", synth.workload_cc_a(v, o), wid_a), ("cc_b", synth.workload_cc_b(v, o), wid_b)):
+        labA, labB, labC, ext = spec
+        t0 = time.time()
+        A, B = synth.make_operands(wid, labA, labB, ext, kind=kind)
+        gen_s = time.time() - t0
+        dA = torch.from_numpy(A).to(dev)
+        dB = torch.from_numpy(B).to(dev)
+        C = tc.empty_colmajor([ext[l] for l in labC], device=dev)
+        C.zero_()
+        work[name] = dict(spec=spec, A=A, B=B, dA=dA, dB=dB, C=C, gen_s=gen_s)
+        log("%s v=%d o=%d inputs ready (%.1f s to generate)" % (name, v, o, gen_s))
+    return work
+
+
+def time_steps(work, plans, steps, warmup, stream):
+    """Warm-up, then exactly `steps` steps (every contraction once) between two
+    device synchronisations; HIP events around each tc_execute on `stream`.
+    Returns (wall seconds, {name: [ms per execution]})."""
+    import torch
+
+    def step(evs=None):
+        for name in work:
+            w, pl = work[name], plans[name]
+            if evs is not None:
+                evs[name][0].record(stream)
+            pl["plan"].execute(w["dA"], w["dB"], pl["C"], 1.0, 0.0, stream=stream, workspace=pl["ws"])
+            if evs is not None:
+                evs[name][1].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evlist = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        evs = {n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for n in work}
+        step(evs)
+        evlist.append(evs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = {n: [evs[n][0].elapsed_time(evs[n][1]) for evs in evlist] for n in work}
+    return wall, per
+
+
+def make_plans(tc, work, precision, dev, reuse_c=False):
+    plans = {}
+    for name, w in work.items():
+        labA, labB, labC, ext = w["spec"]
+        C = w["C"] if reuse_c else tc.empty_colmajor([ext[l] for l in labC], device=dev)
+        plan = tc.Plan.for_tensors(w["dA"], labA, w["dB"], labB, C, labC, precision=precision)
+        plans[name] = dict(plan=plan, C=C, ws=plan.workspace(dev))
+    return plans
+
+
+def close_plans(plans):
+    import torch
+    for pl in plans.values():
+        pl["plan"].close()
+        pl["ws"] = pl["C"] = None
+    torch.cuda.empty_cache()
 
 
 def main():
@@ -97,117 +223,109 @@ def main():
         y.copy_(x)
         torch.neg(x, out=y)
         torch.cuda.synchronize()
-        print("[bench] calibration copies: %d bytes read, %d bytes written each" % (x.numel() * 8, y.numel() * 8),
-              file=sys.stderr, flush=True)
+        log("calibration copies: %d bytes read, %d bytes written each" % (x.numel() * 8, y.numel() * 8))
         del x, y
         torch.cuda.empty_cache()
 
-    work = {}
-    for name, spec, wid in (("cc_a", synth.workload_cc_a(args.v, args.o), 1),
-                            ("cc_b", synth.workload_cc_b(args.v, args.o), 2)):
-        labA, labB, labC, ext = spec
-        t0 = time.time()
-        A, B = synth.make_operands(wid, labA, labB, ext, kind="uniform")
-        dA = torch.from_numpy(A).to(dev)
-        dB = torch.from_numpy(B).to(dev)
-        C = tc.empty_colmajor([ext[l] for l in labC], device=dev)
-        C.zero_()
-        tp = time.perf_counter()
-        plan = tc.Plan.for_tensors(dA, labA, dB, labB, C, labC)
-        plan_ms = (time.perf_counter() - tp) * 1e3
-        work[name] = dict(spec=spec, A=A, B=B, dA=dA, dB=dB, C=C, plan=plan, plan_ms=plan_ms,
-                          ws=plan.workspace(dev), gen_s=time.time() - t0)
-        print("[bench] %s ready: %s" % (name, plan.info.as_dict()), file=sys.stderr, flush=True)
-
+    v, o = args.v, args.o
+    workload = ("coupled-cluster contractions (a) abcd,cdij->abij and (b) akic,kbcj->abij, v=%d o=%d, "
+                "N(0,1)*10^U(-3,3) per last-index slice" % (v, o))
+    work = build_workload(tc, torch, synth, v, o, "scaled_normal", 21, 22, dev)
     stream = torch.cuda.current_stream()
 
-    def step(evs=None):
-        for name in ("cc_a", "cc_b"):
-            w = work[name]
-            if evs is not None:
-                evs[name][0].record(stream)
-            w["plan"].execute(w["dA"], w["dB"], w["C"], 1.0, 0.0, stream=stream, workspace=w["ws"])
-            if evs is not None:
-                evs[name][1].record(stream)
+    if args.profile:
+        plans = make_plans(tc, work, args.profile, dev, reuse_c=True)
+        wall, per = time_steps(work, plans, args.steps, args.warmup, stream)
+        log("profile run %s: %s ms per step" % (args.profile, {n: round(float(np.mean(x)), 3) for n, x in per.items()}))
+        close_plans(plans)
+        return
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    # the oracle's reference for the sampled entries runs on the host while the GPU is timed
+    idx = {n: sample_indices([w["spec"][3][l] for l in w["spec"][2]], 31 + i) for i, (n, w) in enumerate(work.items())}
+    pool = concurrent.futures.ThreadPoolExecutor(1)
+    ref_future = {n: pool.submit(reference_entries, w["A"], w["spec"][0], w["B"], w["spec"][1], w["spec"][2], idx[n])
+                  for n, w in work.items()}
 
-    # timed region: exactly K steps between two device-wide synchronisations
-    per = {n: [] for n in work}
-    evlist = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        evs = {n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for n in work}
-        step(evs)
-        evlist.append(evs)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for evs in evlist:
-        for n in work:
-            per[n].append(evs[n][0].elapsed_time(evs[n][1]))
-
-    flops_step = sum(w["plan"].info.flops for w in work.values())
+    # ---- the timed region: K steps of the FP64 path
+    plans = make_plans(tc, work, "f64", dev, reuse_c=True)
+    for n, pl in plans.items():
+        log("%s plan: %s" % (n, pl["plan"].info.as_dict()))
+    wall, per = time_steps(work, plans, args.steps, args.warmup, stream)
+    flops = {n: pl["plan"].info.flops for n, pl in plans.items()}
+    flops_step = sum(flops.values())
     value = flops_step * args.steps / wall / 1e9
+    log("FP64 step: %.3f ms, %.1f GFLOP/s" % (wall / args.steps * 1e3, value))
+    results = {"f64": dict(step_ms=wall / args.steps * 1e3, per={n: float(np.mean(x)) for n, x in per.items()},
+                           got={n: gather(pl["C"], idx[n]) for n, pl in plans.items()}, digits=None, bits=None)}
+    ia = plans["cc_a"]["plan"].info
+    infos = {n: pl["plan"].info.as_dict() for n, pl in plans.items()}
+    close_plans(plans)
 
-    # accuracy on sampled outputs against the compensated oracle (outside the timed region)
-    import oracle
-    errs = {}
-    for name, w in work.items():
-        labA, labB, labC, ext = w["spec"]
-        shape = [ext[l] for l in labC]
-        g = np.random.default_rng(11)
-        idx = np.stack([g.integers(0, e, 512) for e in shape], axis=1)
-        s, a = oracle.contract_entries(w["A"], labA, w["B"], labB, labC, idx)
-        got = w["C"].cpu().numpy()[tuple(idx.T)]
-        errs[name] = float(np.max(np.abs(got - s) / a))
+    # ---- split precision on the same inputs (each result timed and sampled)
+    if not args.no_split:
+        reps = max(3, min(args.steps, 5))
+        for prec in PRECISIONS[1:]:
+            plans = make_plans(tc, work, prec, dev)
+            w_s, per_s = time_steps(work, plans, reps, 1, stream)
+            results[prec] = dict(step_ms=sum(float(np.mean(x)) for x in per_s.values()),
+                                 per={n: float(np.mean(x)) for n, x in per_s.items()},
+                                 got={n: gather(pl["C"], idx[n]) for n, pl in plans.items()},
+                                 digits=plans["cc_a"]["plan"].info.split_slices,
+                                 bits={n: pl["plan"].info.split_bits for n, pl in plans.items()},
+                                 workspace_gb={n: round(pl["plan"].info.workspace_bytes / 1e9, 3)
+                                               for n, pl in plans.items()})
+            log("%s step: %.3f ms" % (prec, results[prec]["step_ms"]))
+            close_plans(plans)
 
-    per_contraction = {}
-    for name, w in work.items():
-        ms = float(np.mean(per[name]))
-        info = w["plan"].info
-        per_contraction[name] = {
-            "ms": round(ms, 4), "tflops": round(info.flops / ms / 1e9, 3),
-            "frac_fp64_peak": round(info.flops / ms / 1e9 / FP64_PEAK_TFLOPS, 4),
-            "paper_class": info.paper_class, "recipe": tc.RECIPE_NAMES[info.recipe], "tile_id": info.tile_id,
-            "M": info.M, "N": info.N, "K": info.K, "plan_create_ms": round(w["plan_ms"], 3),
-            "max_componentwise_error_sampled": errs[name],
-        }
+    refs = {n: f.result() for n, f in ref_future.items()}
+    pool.shutdown()
+    summary = {}
+    for prec, r in results.items():
+        per_c = {}
+        for n in work:
+            comp, norm = errors(r["got"][n], refs[n])
+            per_c[n] = {"ms": round(r["per"][n], 4), "effective_tflops": round(flops[n] / r["per"][n] / 1e9, 3),
+                        "max_componentwise_error": comp, "normwise_error": norm}
+            if prec != "f64":
+                per_c[n]["bits"] = r["bits"][n]
+                per_c[n]["workspace_gb"] = r["workspace_gb"][n]
+        summary[prec] = {"step_ms": round(r["step_ms"], 4), "gflops": round(flops_step / r["step_ms"] / 1e6, 1),
+                         "speedup_vs_f64": round(results["f64"]["step_ms"] / r["step_ms"], 3),
+                         "digits_or_moduli": r["digits"],
+                         "max_componentwise_error": max(c["max_componentwise_error"] for c in per_c.values()),
+                         "per_contraction": per_c}
+        log("%s: %s" % (prec, summary[prec]))
+    fp64_err = summary["f64"]["max_componentwise_error"]
 
     # dominant kernel: the GEMM launch of contraction (a)
-    ia = work["cc_a"]["plan"].info
-    ms_a = float(np.mean(per["cc_a"]))
+    ms_a = results["f64"]["per"]["cc_a"]
     achieved = ia.flops / (ms_a * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic_from_profile(GETT_SOURCES),
-                "kernel": "%s (contraction a)" % ("gett_f64_dma_kernel" if ia.copy_fed else "gett_f64_kernel"),
-                "algorithmic_flops_per_launch": ia.flops,
-                "algorithmic_bytes_per_launch": ia.bytes}
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": traffic_from_profile(GETT_SOURCES, "cc_a v=%d o=%d" % (v, o)),
+                "kernel": "%s (contraction a, v=%d o=%d)" % ("gett_f64_dma_kernel" if ia.copy_fed else "gett_f64_kernel",
+                                                            v, o),
+                "algorithmic_flops_per_launch": ia.flops, "algorithmic_bytes_per_launch": ia.bytes}
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(work["cc_a"], args.cpu_seconds)
+        cpu = cpu_baseline(work["cc_a"], ia.K, args.cpu_seconds, flops_step)
 
-    split = None
-    if not args.no_split:
-        split = split_runs(work, max(3, min(args.steps, 10)))
+    n_samples = {n: int(idx[n].shape[0]) for n in work}
+    for w in work.values():
+        for key in ("dA", "dB", "C"):
+            w[key] = None
+    del work
+    torch.cuda.empty_cache()
 
+    c1 = None
+    if not args.no_c1:
+        c1 = c1_runs(args, dev, stream)
     batch = memory = modes = None
     if not args.no_batch:
         batch = batch_runs()
         memory = memory_bound_runs()
         modes = timing_modes_runs()
-
-    precision_workload = None
-    if args.precision_workload:
-        for w in work.values():
-            w["plan"].close()
-            for key in ("dA", "dB", "C", "ws"):
-                w[key] = None
-        torch.cuda.empty_cache()
-        precision_workload = precision_runs(args)
 
     out = {
         "metric": "contraction GFLOP/s (FP64 vs split-BF16) at stated rel. error; % MFMA peak",
@@ -221,15 +339,19 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded uniform[-1,1], column-major FP64)",
-        "config": {"workload": "coupled-cluster contractions (a) abcd,cdij->abij and (b) akic,kbcj->abij, "
-                               "v=%d o=%d, FP64" % (args.v, args.o),
-                   "v": args.v, "o": args.o, "flops_per_step": flops_step},
+        "data": "synthetic (seeded N(0,1) scaled per last-index slice by 10^U(-3,3), column-major FP64)",
+        "config": {"workload": workload, "v": v, "o": o, "flops_per_step": flops_step},
         "frac_fp64_peak": round(value / 1e3 / FP64_PEAK_TFLOPS, 4),
-        "max_componentwise_error": max(errs.values()),
-        "per_contraction": per_contraction,
-        "split_precision": split,
-        "precision_workload": precision_workload,
+        "max_componentwise_error": fp64_err,
+        "split_bf16_gflops": summary.get("split_bf16", {}).get("gflops"),
+        "split_bf16_vs_f64": summary.get("split_bf16", {}).get("speedup_vs_f64"),
+        "split_bf16_max_componentwise_error": summary.get("split_bf16", {}).get("max_componentwise_error"),
+        "results": summary,
+        "error_sample": {"entries_per_contraction": n_samples, "reference": "oracle, compensated (Dot2) sums",
+                         "design": "one row per 128-row block x one column per 10-column block of C "
+                                   "(rows = first two modes), plus two full slabs C[a0,b0,:,:]"},
+        "plans": infos,
+        "c1_workload": c1,
         "batch_workload": batch,
         "memory_bound_kernels": memory,
         "warm_cold_graph": modes,
@@ -237,103 +359,46 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    for w in work.values():
-        w["plan"].close()
 
 
-def sampled_error(A, labA, B, labB, labC, ext, C_dev, n=512, seed=11):
-    """Max componentwise error of C_dev against the compensated oracle on n
-    sampled output entries (each computed in full by the oracle)."""
+def c1_runs(args, dev, stream):
+    """The same two contractions at v = 128, o = 32 on uniform [-1, 1] inputs:
+    FP64 step and the split forms, each with its error on 512 random outputs."""
     import numpy as np
 
     import oracle
-    shape = [ext[l] for l in labC]
-    g = np.random.default_rng(seed)
-    idx = np.stack([g.integers(0, e, n) for e in shape], axis=1)
-    s, a = oracle.contract_entries(A, labA, B, labB, labC, idx)
-    got = C_dev.cpu().numpy()[tuple(idx.T)]
-    return float(np.max(np.abs(got - s) / a))
-
-
-def time_plan(plan, dA, dB, C, reps, stream):
-    import numpy as np
-    import torch
-    ws = plan.workspace(C.device)
-    plan.execute(dA, dB, C, 1.0, 0.0, stream=stream, workspace=ws)
-    torch.cuda.synchronize()
-    ms = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        plan.execute(dA, dB, C, 1.0, 0.0, stream=stream, workspace=ws)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms.append(e0.elapsed_time(e1))
-    return float(np.mean(ms))
-
-
-def split_runs(work, reps):
-    """Split-precision (BF16 and FP8 digits, INT8 residues) on the same inputs:
-    time (HIP events around each tc_execute, split pass included) and sampled
-    error."""
-    import torch
-
-    import paper_1307_2100_amd as tc
-    stream = torch.cuda.current_stream()
-    out = {}
-    for prec in ("split_bf16", "split_fp8", "crt_int8"):
-        res = {}
-        for name, w in work.items():
-            labA, labB, labC, ext = w["spec"]
-            C = tc.empty_colmajor([ext[l] for l in labC], device=w["C"].device)
-            plan = tc.Plan.for_tensors(w["dA"], labA, w["dB"], labB, C, labC, precision=prec)
-            ms = time_plan(plan, w["dA"], w["dB"], C, reps, stream)
-            err = sampled_error(w["A"], labA, w["B"], labB, labC, ext, C)
-            res[name] = {"ms": round(ms, 4), "effective_tflops": round(plan.info.flops / ms / 1e9, 3),
-                         "digits": plan.info.split_slices, "bits": plan.info.split_bits,
-                         "max_componentwise_error_sampled": err,
-                         "workspace_gb": round(plan.info.workspace_bytes / 1e9, 3)}
-            plan.close()
-            del C
-        out[prec] = res
-    return out
-
-
-def precision_runs(args):
-    """The precision workload: both coupled-cluster contractions at v=192,
-    o=48 with N(0,1) inputs scaled per last-index slice by 10^U(-3,3), in FP64,
-    split BF16, split FP8 and INT8 residues, each with its sampled error
-    against the oracle."""
-    import torch
-
     import paper_1307_2100_amd as tc
     import synth
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
+    import torch
+    work = build_workload(tc, torch, synth, 128, 32, "uniform", 1, 2, dev)
     out = {}
-    for name, spec, wid in (("cc_a", synth.workload_cc_a(192, 48), 21), ("cc_b", synth.workload_cc_b(192, 48), 22)):
-        labA, labB, labC, ext = spec
-        A, B = synth.make_operands(wid, labA, labB, ext, kind="scaled_normal")
-        dA = torch.from_numpy(A).to(dev)
-        dB = torch.from_numpy(B).to(dev)
-        C = tc.empty_colmajor([ext[l] for l in labC], device=dev)
-        res = {}
-        for prec in ("f64", "split_bf16", "split_fp8", "crt_int8"):
-            plan = tc.Plan.for_tensors(dA, labA, dB, labB, C, labC, precision=prec)
-            ms = time_plan(plan, dA, dB, C, 3, stream)
-            err = sampled_error(A, labA, B, labB, labC, ext, C, n=256)
-            res[prec] = {"ms": round(ms, 3), "effective_tflops": round(plan.info.flops / ms / 1e9, 3),
-                         "max_componentwise_error_sampled": err,
-                         "digits": plan.info.split_slices if prec != "f64" else None,
-                         "bits": plan.info.split_bits if prec != "f64" else None}
-            plan.close()
-            torch.cuda.empty_cache()
-        res["speedup_split_bf16_vs_f64"] = round(res["f64"]["ms"] / res["split_bf16"]["ms"], 3)
-        res["speedup_crt_int8_vs_f64"] = round(res["f64"]["ms"] / res["crt_int8"]["ms"], 3)
-        out[name] = res
-        print("[bench] precision workload %s: %s" % (name, res), file=sys.stderr, flush=True)
-        del dA, dB, C
-        torch.cuda.empty_cache()
+    flops = None
+    for prec in PRECISIONS if not args.no_split else PRECISIONS[:1]:
+        plans = make_plans(tc, work, prec, dev)
+        flops = {n: pl["plan"].info.flops for n, pl in plans.items()}
+        steps = args.steps if prec == "f64" else 5
+        wall, per = time_steps(work, plans, steps, 2, stream)
+        res = {"step_ms": round(sum(float(np.mean(x)) for x in per.values()), 4)}
+        for n, pl in plans.items():
+            labA, labB, labC, ext = work[n]["spec"]
+            shape = [ext[l] for l in labC]
+            g = np.random.default_rng(11)
+            idx = np.stack([g.integers(0, e, 512) for e in shape], axis=1)
+            ref = oracle.contract_entries(work[n]["A"], labA, work[n]["B"], labB, labC, idx)
+            comp, _ = errors(gather(pl["C"], idx), ref)
+            res[n] = {"ms": round(float(np.mean(per[n])), 4),
+                      "effective_tflops": round(flops[n] / float(np.mean(per[n])) / 1e9, 3),
+                      "max_componentwise_error_sampled": comp, "tile_id": pl["plan"].info.tile_id,
+                      "copy_fed": pl["plan"].info.copy_fed}
+        res["gflops"] = round(sum(flops.values()) / res["step_ms"] / 1e6, 1)
+        out[prec] = res
+        log("c1 %s: %s" % (prec, res))
+        close_plans(plans)
+    for w in work.values():
+        for key in ("dA", "dB", "C"):
+            w[key] = None
+    torch.cuda.empty_cache()
+    out["workload"] = "coupled-cluster (a)+(b), v=128 o=32, uniform[-1,1]"
     return out
 
 
@@ -552,16 +617,16 @@ def memory_bound_runs(reps=20):
     return out
 
 
-def cpu_baseline(w, target_s):
+def cpu_baseline(w, K, target_s, flops_step):
     """The oracle (plain FP64 nested loop, all host threads it uses) on a
     bounded sample of contraction (a): whole output entries, each a full
-    K-long sum, timed and scaled to GFLOP/s."""
+    K-long sum, timed and scaled to GFLOP/s; the full step's oracle time is
+    extrapolated from that rate."""
     import numpy as np
 
     import oracle
     labA, labB, labC, ext = w["spec"]
     shape = [ext[l] for l in labC]
-    K = w["plan"].info.K
     g = np.random.default_rng(3)
     n = 64
     while True:
@@ -574,7 +639,10 @@ def cpu_baseline(w, target_s):
         n = int(n * min(16.0, max(2.0, target_s / max(dt, 1e-3))))
     gflops = 2.0 * K * n / dt / 1e9
     return {"value": round(gflops, 4), "unit": "GFLOP/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": "%d output entries of contraction (a) (each a %d-term sum), %.1f s" % (n, K, dt)}
+            "sample": "%d random output entries of contraction (a) (each a %d-term plain FP64 sum), %.1f s; "
+                      "the whole step (a)+(b) would take %.0f s at this rate (extrapolated)"
+                      % (n, K, dt, flops_step / (gflops * 1e9)),
+            "extrapolated_step_s": round(flops_step / (gflops * 1e9), 1)}
 
 
 if __name__ == "__main__":

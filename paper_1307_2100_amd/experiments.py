@@ -39,6 +39,9 @@ import torch
 
 import paper_1307_2100_amd as tc
 
+FP64_PEAK_TFLOPS = 78.6   # MI355X, dense FP64 MFMA
+HBM_PEAK_GBS = 8000.0     # MI355X, HBM3E
+
 RECIPES = {"square": ("gemm", "copy_gemm", "gemv", "ger"),
            "cc": ("gemm", "copy_gemm", "dot", "ger"),
            "gr": ("gemm", "copy_gemm", "dot", "ger")}
@@ -74,11 +77,16 @@ def _shape(lab, ext):
     return [ext[l] for l in lab]
 
 
-def run_recipes(study, la, lb, lc, ext, recipes, seed):
-    """One contraction under the rules and under each forced recipe."""
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
-    A, B = _uniform(_shape(la, ext), gen), _uniform(_shape(lb, ext), gen)
+def run_recipes(study, la, lb, lc, ext, recipes, seed, inputs=None, keep_outputs=False):
+    """One contraction under the rules and under each forced recipe.  inputs:
+    optional (A, B) device tensors to use instead of seeded uniform ones;
+    keep_outputs: each row also holds its result tensor under "C"."""
+    if inputs is None:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        A, B = _uniform(_shape(la, ext), gen), _uniform(_shape(lb, ext), gen)
+    else:
+        A, B = inputs
     K = 1
     for l in la:
         if l in lb and l not in lc:
@@ -98,27 +106,37 @@ def run_recipes(study, la, lb, lc, ext, recipes, seed):
             diff = 0.0
         else:
             diff = float((C - ref).abs().max()) / K if C.numel() else 0.0
-            del C
         row = {"study": study, "contraction": "%s,%s->%s" % (la, lb, lc),
                "extents": {l: ext[l] for l in sorted(ext)}, "recipe": recipe,
                "ran": tc.RECIPE_NAMES[info.recipe], "paper_class": info.paper_class,
                "kernel": tc.KERNEL_NAMES.get(info.kernel, "?"), "ms": round(ms, 4), "reps": reps,
                "gflops": round(info.flops / ms / 1e6, 2), "max_diff_over_K": diff}
+        bound_ms = max(info.flops / (FP64_PEAK_TFLOPS * 1e9), info.bytes / (HBM_PEAK_GBS * 1e6))
+        row["frac_roofline"] = round(bound_ms / ms, 4) if ms > 0 else None
         print(json.dumps(row), flush=True)
         if diff > 1e-12:
             raise RuntimeError("recipe %s disagrees with the rules' result: %.3e" % (recipe, diff))
+        if keep_outputs:
+            row["C"] = C
+        elif C is not ref:
+            del C
         rows.append(row)
     del A, B, ref
     torch.cuda.empty_cache()
     return rows
 
 
-def run_layout(la, lb, lc, ext, seed):
-    """A contraction timed in the given layout and in the suggested one."""
+def run_layout(la, lb, lc, ext, seed, inputs=None, keep_outputs=False):
+    """A contraction timed in the given layout and in the suggested one
+    (inputs and keep_outputs as for run_recipes; each kept result is viewed in
+    the given output's label order)."""
     out, info = tc.suggest_layout(la, _shape(la, ext), lb, _shape(lb, ext), lc, _shape(lc, ext))
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
-    A, B = _uniform(_shape(la, ext), gen), _uniform(_shape(lb, ext), gen)
+    if inputs is None:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        A, B = _uniform(_shape(la, ext), gen), _uniform(_shape(lb, ext), gen)
+    else:
+        A, B = inputs
     rows = []
     results = {}
     for which, (xa, xb, xc) in (("given", (la, lb, lc)), ("suggested", (out["A"], out["B"], out["C"]))):
@@ -152,6 +170,8 @@ def run_layout(la, lb, lc, ext, seed):
     rows[-1]["max_diff_over_K"] = diff
     if diff > 1e-12:
         raise RuntimeError("suggested layout disagrees with the given one: %.3e" % diff)
+    if keep_outputs:
+        rows[0]["C"], rows[1]["C"] = results["given"], results["suggested"]
     del A, B, results
     torch.cuda.empty_cache()
     return rows

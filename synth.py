@@ -19,30 +19,84 @@ def rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
 
+# Large tensors are drawn in chunks of CHUNK consecutive entries (storage
+# order), chunk c from PCG64(seed) advanced by c jumps of 2^127 draws (chunk 0
+# from PCG64(seed) itself), so they can be filled by several threads and the
+# values do not depend on the thread count.  A tensor of at most CHUNK
+# entries is one plain PCG64(seed) stream.
+CHUNK = 1 << 22
+
+
+def _workers():
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _chunked(shape, seed, draw):
+    """Column-major FP64 array of `shape`; draw(gen, out) fills one chunk."""
+    n = int(np.prod(shape, dtype=np.int64))
+    x = np.empty(n, dtype=np.float64)
+    nchunks = (n + CHUNK - 1) // CHUNK
+
+    def job(c):
+        g = rng(seed) if c == 0 else np.random.Generator(np.random.PCG64(seed).jumped(c))
+        draw(g, x[c * CHUNK:(c + 1) * CHUNK], c * CHUNK)
+
+    if nchunks <= 1:
+        if n:
+            job(0)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(_workers()) as ex:
+            list(ex.map(job, range(nchunks)))
+    return x.reshape(shape, order="F")
+
+
 def uniform(shape, seed, lo=-1.0, hi=1.0):
     """Entries uniform in [lo, hi), column-major FP64."""
-    x = rng(seed).uniform(lo, hi, size=int(np.prod(shape, dtype=np.int64)))
-    return x.reshape(shape, order="F")
+    def draw(g, out, start):
+        out[:] = g.uniform(lo, hi, size=out.size)
+    return _chunked(shape, seed, draw)
 
 
 def integers(shape, seed, lo=-4, hi=4):
     """Integer-valued FP64 entries in [lo, hi]: every partial sum of products of
     such values is exact in FP64 (and in BF16/FP8 slices), so results computed
     in any order agree bit for bit."""
-    x = rng(seed).integers(lo, hi + 1, size=int(np.prod(shape, dtype=np.int64))).astype(np.float64)
-    return x.reshape(shape, order="F")
+    def draw(g, out, start):
+        out[:] = g.integers(lo, hi + 1, size=out.size)
+    return _chunked(shape, seed, draw)
 
 
 def scaled_normal(shape, seed, axis=-1, decades=3.0):
     """N(0,1) entries, each slice along `axis` scaled by 10^U(-decades, decades)
-    (one factor drawn per slice), column-major FP64."""
-    g = rng(seed)
-    x = g.standard_normal(size=int(np.prod(shape, dtype=np.int64))).reshape(shape, order="F")
+    (one factor drawn per slice, from its own stream: PCG64(seed) advanced by
+    as many jumps as the tensor has chunks), column-major FP64."""
+    shape = tuple(int(e) for e in shape)
     axis = axis % len(shape)
-    f = 10.0 ** g.uniform(-decades, decades, size=shape[axis])
-    bshape = [1] * len(shape)
-    bshape[axis] = shape[axis]
-    return np.asfortranarray(x * f.reshape(bshape))
+    n = int(np.prod(shape, dtype=np.int64))
+    nchunks = max(1, (n + CHUNK - 1) // CHUNK)
+    f = np.random.Generator(np.random.PCG64(seed).jumped(nchunks)).uniform(-decades, decades, size=shape[axis])
+    f = 10.0 ** f
+    inner = int(np.prod(shape[:axis], dtype=np.int64))   # entries per step of the axis (column-major)
+    extent = shape[axis]
+
+    def draw(g, out, start):
+        g.standard_normal(out=out)
+        if inner >= 1024:   # long runs of one factor: scale run by run
+            q = start
+            while q < start + out.size:
+                stop = min(start + out.size, (q // inner + 1) * inner)
+                out[q - start:stop - start] *= f[(q // inner) % extent]
+                q = stop
+        else:
+            out *= f[(np.arange(start, start + out.size, dtype=np.int64) // inner) % extent]
+
+    return _chunked(shape, seed, draw)
 
 
 # Workloads: (labels A, labels B, labels C, extents per label).  Labels are
@@ -134,3 +188,36 @@ def random_contraction(g, rank_range=(3, 6), ext_range=(4, 64), max_elems=1 << 2
         if max(size(la), size(lb), size(lc)) > max_elems:
             continue
         return "".join(la), "".join(lb), "".join(lc), ext
+
+
+def unravel_colmajor(lin, extents):
+    """Column-major multi-indices (n, len(extents)) of linear indices."""
+    lin = np.asarray(lin, dtype=np.int64)
+    out = np.empty((lin.size, len(extents)), dtype=np.int64)
+    for d, e in enumerate(extents):
+        out[:, d] = lin % e
+        lin = lin // e
+    return out
+
+
+def stratified_entries(shape, split, row_block, col_block, seed):
+    """Output entries on a stratified grid: the modes of C before `split` form
+    the row index, the rest the column index (each linearised column-major).
+    One row is drawn uniformly inside every block of row_block consecutive
+    rows, one column inside every block of col_block columns, and every
+    (row, column) pair is returned, rows outermost, as an (n, len(shape))
+    multi-index array.  Any tile of at least row_block x col_block aligned
+    entries therefore holds a sample, and consecutive entries share a row."""
+    g = rng(seed)
+    nr = int(np.prod(shape[:split], dtype=np.int64))
+    nc = int(np.prod(shape[split:], dtype=np.int64))
+
+    def pick(n, block):
+        starts = np.arange(0, n, block, dtype=np.int64)
+        width = np.minimum(block, n - starts)
+        return starts + (g.random(starts.size) * width).astype(np.int64)
+
+    rows, cols = pick(nr, row_block), pick(nc, col_block)
+    r = np.repeat(rows, cols.size)
+    c = np.tile(cols, rows.size)
+    return np.concatenate([unravel_colmajor(r, shape[:split]), unravel_colmajor(c, shape[split:])], axis=1)

@@ -192,3 +192,53 @@ def test_split_rejects_batch_and_too_many_digits():
         tc.Plan.for_tensors(A[:, :, 0], "ik", B[:, :, 0], "kj", C[:, :, 0], "ij", precision="split_bf16",
                             split_slices=9)
     assert e.value.status == tc.TC_ERR_INVALID_ARG
+
+
+# FP8 digits at the default S = 8 keep 4 + 5*7 = 39 bits of each input below its
+# row's power-of-two scale.  Bounds held here (componentwise, against the
+# compensated oracle): 1e-10 on uniform inputs, 1e-9 on inputs whose slices
+# are scaled by 10^U(-3,3) (a row then mixes entries six decades apart, and
+# the small ones keep fewer bits of their own).
+FP8_TOL_UNIFORM = 1e-10
+FP8_TOL_SCALED = 1e-9
+
+
+@pytest.mark.parametrize("kind,tol", [("uniform", FP8_TOL_UNIFORM), ("scaled_normal", FP8_TOL_SCALED)])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_split_fp8_default_meets_its_bound(case, kind, tol):
+    name, labA, labB, labC, ext = case
+    A, B = synth.make_operands(32, labA, labB, ext, kind=kind)
+    got, info = _run(labA, labB, labC, A, B, "split_fp8")
+    assert info["split_slices"] == 8
+    ref, absr = reference(A, labA, B, labB, labC)
+    err = componentwise_error(got, ref, absr)
+    print(name, kind, "fp8 S=8 componentwise error %.3e" % err)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("precision", ["split_fp8", "split_bf16"])
+def test_split_long_contraction_flushes_level_sums(precision):
+    """A contracted range of 9000 indices: the FP8 kernel moves its FP32 level
+    sums to FP64 every 4096 indices (BF16: every 64 to 256), so the flush runs
+    twice and ends on a partial chunk.  Exact on integers (the FP32 level
+    sums of up to 4096 products of digits below 2^4 stay below 2^24), within
+    the bound otherwise."""
+    labA, labB, labC = "ik", "kj", "ij"
+    ext = {"i": 70, "k": 9000, "j": 50}
+    A, B = synth.make_operands(33, labA, labB, ext, kind="integers")
+    got, info = _run(labA, labB, labC, A, B, precision)
+    assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
+    # integers up to 2^4 in both inputs: the largest level-0 products of FP8
+    # digits, summed over the whole flush chunk
+    A = np.full((70, 9000), 15.0, order="F")
+    B = np.full((9000, 50), -15.0, order="F")
+    got, info = _run(labA, labB, labC, A, B, precision)
+    assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
+    tol = {"split_fp8": (FP8_TOL_UNIFORM, FP8_TOL_SCALED), "split_bf16": (SPLIT_TOL, SPLIT_TOL)}[precision]
+    for kind, t in zip(("uniform", "scaled_normal"), tol):
+        A, B = synth.make_operands(34, labA, labB, ext, kind=kind)
+        got, info = _run(labA, labB, labC, A, B, precision)
+        ref, absr = reference(A, labA, B, labB, labC)
+        err = componentwise_error(got, ref, absr)
+        print(precision, kind, "K=9000 componentwise error %.3e" % err)
+        assert err <= t
