@@ -106,6 +106,11 @@ typedef struct {
   int tile_id;                 /* GEMM tile configuration; -1 = chosen by the picker.  For
                                   TC_PREC_F64_CRT_INT8 plans: residue GEMM configuration, 0 to
                                   TC_CRT_NUM_TILES - 1, -1 = the default */
+  int copy_tile;               /* output tile of the copy-fed FP64 kernel (taken for the 256x128 and
+                                  128x256 tiles when tc_plan_info.copy_fed is set): 0 256x128, 1 128x256,
+                                  2 192x192; -1 (default) = the tile_id's own shape when tile_id is given,
+                                  else the shape whose workgroups, dealt out one per compute unit in
+                                  rounds, leave the least output area in flight */
 } tc_options;
 
 typedef struct {
@@ -128,8 +133,10 @@ typedef struct {
   int picked_candidate;        /* candidate chosen by the MLP or the tune cache, -1: rules */
   int split_bits;              /* split precision: bits each input keeps relative to its row's power-of-two
                                   scale (every input is exact to 2^-split_bits of that scale), 0 otherwise */
-  int copy_fed;                /* 1: the GEMM runs the kernel fed by direct global-to-LDS copies (operand
-                                  layouts allow 16-byte pairs; taken when A and B are 16-byte aligned) */
+  int copy_fed;                /* nonzero: the GEMM runs the kernel fed by direct global-to-LDS copies
+                                  (operand layouts allow 16-byte pairs; taken when A and B, after any
+                                  COPY step, are 16-byte aligned), with output tiles of 256x128 (1),
+                                  128x256 (2) or 192x192 (3); 0: the gathering GEMM kernel or another */
 } tc_plan_info;
 
 /* Fills *opt with the defaults listed in tc_options. */

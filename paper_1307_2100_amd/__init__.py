@@ -54,7 +54,7 @@ PICKERS = {"rules": 0, "mlp": 1, "tuned": 2}
 
 class tc_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("recipe", ctypes.c_int), ("picker", ctypes.c_int),
-                ("split_slices", ctypes.c_int), ("tile_id", ctypes.c_int)]
+                ("split_slices", ctypes.c_int), ("tile_id", ctypes.c_int), ("copy_tile", ctypes.c_int)]
 
 
 class tc_plan_info(ctypes.Structure):
@@ -213,7 +213,11 @@ class Desc:
         return cls(list(t.shape), list(t.stride()), labels)
 
 
-def make_options(precision="f64", recipe="auto", picker=0, split_slices=0, tile_id=-1):
+# output tiles of the copy-fed FP64 kernel (tc_options.copy_tile, tc_plan_info.copy_fed - 1)
+COPY_TILES = {"256x128": 0, "128x256": 1, "192x192": 2}
+
+
+def make_options(precision="f64", recipe="auto", picker=0, split_slices=0, tile_id=-1, copy_tile=-1):
     o = tc_options()
     _lib.tc_options_default(ctypes.byref(o))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -221,6 +225,7 @@ def make_options(precision="f64", recipe="auto", picker=0, split_slices=0, tile_
     o.picker = PICKERS[picker] if isinstance(picker, str) else int(picker)
     o.split_slices = int(split_slices)
     o.tile_id = int(tile_id)
+    o.copy_tile = COPY_TILES[copy_tile] if isinstance(copy_tile, str) else int(copy_tile)
     return o
 
 
@@ -348,8 +353,9 @@ def _require_f64_cuda(t, name):
 class Plan:
     """A libtc plan for fixed extents, strides and labels of A, B and C."""
 
-    def __init__(self, dA, dB, dC, precision="f64", recipe="auto", tile_id=-1, split_slices=0, picker=0):
-        self.options = make_options(precision, recipe, picker, split_slices, tile_id)
+    def __init__(self, dA, dB, dC, precision="f64", recipe="auto", tile_id=-1, split_slices=0, picker=0,
+                 copy_tile=-1):
+        self.options = make_options(precision, recipe, picker, split_slices, tile_id, copy_tile)
         self.handle = tc_plan_create(dA, dB, dC, self.options)
         self.info = tc_plan_query(self.handle)
         self._ws = None

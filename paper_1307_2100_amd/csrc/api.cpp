@@ -612,6 +612,7 @@ void tc_options_default(tc_options* opt) {
   opt->picker = TC_PICKER_RULES;
   opt->split_slices = 0;
   opt->tile_id = -1;
+  opt->copy_tile = -1;
 }
 
 tc_status tc_analyze(int ra, const int64_t* ea, const int64_t* sa, const int32_t* la, int rb, const int64_t* eb,
@@ -695,6 +696,10 @@ tc_status tc_plan_create(tc_plan_t* out, int ra, const int64_t* ea, const int64_
       tc::Analysis an2;
       std::string err;
       if (tc::analyze(p->desc[0], p->desc[1], p->desc[2], o, &an2, &err) == TC_OK) {
+        if (an2.dma_ok && p->opt.copy_tile < 0) {  // the picker chooses the tile; the copy-fed output tile follows the round rule
+          an2.dma_shape = tc::dma_shape(an2.info.M, an2.info.N, an2.info.L);
+          an2.info.copy_fed = 1 + an2.dma_shape;
+        }
         p->an = an2;
         p->an.info.picked_candidate = c;
         break;
@@ -875,12 +880,13 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
   }
   int tile = info.tile_id >= 0 ? info.tile_id : 1;
   double* parts = info.k_split > 1 ? (double*)((char*)workspace + an.part_offset) : nullptr;
-  // the copy-fed kernel needs the caller's operands (no COPY step) on 16-byte boundaries
-  const bool dma = an.dma_ok && an.copy_slot < 0 && ((reinterpret_cast<uintptr_t>(KA) | reinterpret_cast<uintptr_t>(KB)) & 15) == 0;
+  // the copy-fed kernel needs both operands (after any COPY step) on 16-byte boundaries
+  const bool dma = an.dma_ok && ((reinterpret_cast<uintptr_t>(KA) | reinterpret_cast<uintptr_t>(KB)) & 15) == 0;
   tc::DmaK dk{};
   if (dma) {
     const tc::Group& gk = an.g[tc::GK];
     dk.n = gk.n;
+    dk.shape = an.dma_shape;
     for (int i = 0; i < gk.n && i < tc::kDmaMaxKModes; ++i) {
       dk.ext[i] = gk.ext[i];
       dk.sa[i] = gk.str[tc::SA][i];

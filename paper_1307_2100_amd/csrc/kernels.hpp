@@ -35,6 +35,7 @@ namespace tc {
 
 constexpr int kMaxRank = 16;
 
+
 // Offsets of one operand along one index group: a table of per-index
 // offsets, or (tab == nullptr) an affine map idx * stride.
 // Division by a divisor fixed at plan time, for 0 <= n < 2^31: multiply by
@@ -123,23 +124,48 @@ constexpr TileCfg kTiles[] = {TC_GETT_TILES(TC_TILE_ENTRY)};
 #undef TC_TILE_ENTRY
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
-// The tile whose layout-eligible launches (see Analysis::dma_ok) run the
-// copy-fed kernel.
+// The large tiles (256 x 128 and 128 x 256) whose layout-eligible launches
+// (see Analysis::dma_ok) run the copy-fed kernel.
 constexpr int kDmaTile = 11;
+constexpr int kDmaTileWide = 12;
+// Output tiles of the copy-fed kernel, all 8 wavefronts over a 144 KB LDS
+// ring: 256 x 128, 128 x 256 and 192 x 192.
+enum { kDma256x128 = 0, kDma128x256 = 1, kDma192x192 = 2, kDmaShapes = 3 };
+constexpr int kDmaShapeBM[kDmaShapes] = {256, 128, 192};
+constexpr int kDmaShapeBN[kDmaShapes] = {128, 256, 192};
+// Compute units of the target (MI355X): one copy-fed workgroup runs per unit.
+constexpr int kDmaComputeUnits = 256;
+// Copy-fed shape for an (M, N, L) output: the one among the three whose
+// workgroups, dealt out in rounds of one per compute unit, leave the least
+// output area in flight (rounds x tile area); ties keep the lower index.
+inline int dma_shape(int64_t M, int64_t N, int64_t L) {
+  int best = 0;
+  double cost = 0.0;
+  for (int s = 0; s < kDmaShapes; ++s) {
+    const int64_t tiles = ((M + kDmaShapeBM[s] - 1) / kDmaShapeBM[s]) * ((N + kDmaShapeBN[s] - 1) / kDmaShapeBN[s]) * L;
+    const double c = (double)((tiles + kDmaComputeUnits - 1) / kDmaComputeUnits) * kDmaShapeBM[s] * kDmaShapeBN[s];
+    if (s == 0 || c < cost) {
+      best = s;
+      cost = c;
+    }
+  }
+  return best;
+}
 // Contracted group of the copy-fed kernel as modes (first fastest): the
 // offset of k is computed from its digits, so no table lookup (a dependent
 // load) sits in front of a copy.
 constexpr int kDmaMaxKModes = 4;
 struct DmaK {
   int n;
+  int shape;                  // kDma256x128, kDma128x256 or kDma192x192
   int64_t ext[kDmaMaxKModes];
   int64_t sa[kDmaMaxKModes];  // strides in the kernel's A
   int64_t sb[kDmaMaxKModes];  // strides in the kernel's B
 };
 // split > 1: the contracted range is cut into `split` segments of seg_len
 // (a multiple of the tile depth); parts holds tiles * split * BM * BN doubles.
-// dma: the operands qualify for the copy-fed kernel (used for kDmaTile
-// without split).
+// dma: the operands qualify for the copy-fed kernel (used for the large
+// tiles without split); it runs in dma->shape.
 hipError_t launch_gett_f64(const GettParams& p, int tile_id, bool a_kfast, bool b_kfast, int split, int64_t seg_len,
                            double* parts, hipStream_t s, const DmaK* dma = nullptr);
 // Split-K choice for `tiles` output tiles of depth-`bk` steps over K.

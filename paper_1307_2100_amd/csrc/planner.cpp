@@ -385,7 +385,8 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
     }
   }
   if (opt.precision < TC_PREC_F64 || opt.precision > TC_PREC_F64_CRT_INT8 || opt.recipe < TC_RECIPE_AUTO ||
-      opt.recipe > TC_RECIPE_DOT || opt.tile_id < -1 || opt.tile_id >= kNumTiles || opt.split_slices < 0) {
+      opt.recipe > TC_RECIPE_DOT || opt.tile_id < -1 || opt.tile_id >= kNumTiles || opt.split_slices < 0 ||
+      opt.copy_tile < -1 || opt.copy_tile >= kDmaShapes) {
     *err = "invalid tc_options field";
     return TC_ERR_INVALID_ARG;
   }
@@ -706,8 +707,16 @@ tc_status analyze(const TensorDesc& A0, const TensorDesc& B0, const TensorDesc& 
       }
       info.workspace_bytes = ws;
     }
-    an.dma_ok = an.dma_ok && recipe == TC_RECIPE_GEMM && split == 1 && info.tile_id == kDmaTile;
-    info.copy_fed = an.dma_ok ? 1 : 0;
+    // the copy-fed kernel stands in for the large tiles (also after the copy
+    // of COPY+GEMM, whose packed operand qualifies like any other); its
+    // output tile follows the tile asked for, else the round rule
+    an.dma_ok = an.dma_ok && (recipe == TC_RECIPE_GEMM || recipe == TC_RECIPE_COPY_GEMM) && split == 1 &&
+                (info.tile_id == kDmaTile || info.tile_id == kDmaTileWide);
+    if (an.dma_ok)
+      an.dma_shape = opt.copy_tile >= 0 ? opt.copy_tile
+                     : opt.tile_id < 0  ? dma_shape(info.M, info.N, info.L)
+                                        : (info.tile_id == kDmaTile ? kDma256x128 : kDma128x256);
+    info.copy_fed = an.dma_ok ? 1 + an.dma_shape : 0;
   } else {
     // Memory-bound recipes (Sec. 3.2, Classes 1 and 2, and the GER slicing).
     // GER sums its rank-1 updates in registers, one thread per output entry.

@@ -71,6 +71,7 @@ struct Analysis {
   // other stride is even) and the contracted group has at most
   // kDmaMaxKModes modes
   bool dma_ok = false;
+  int dma_shape = 0;        // copy-fed output tile (kDma256x128, kDma128x256, kDma192x192)
   // split precision: padded sizes of the digit planes and workspace offsets
   int slices = 0;
   int crt_bits = 0;         // residue form: bits of the integer inputs

@@ -301,16 +301,18 @@ def test_crt_plan_bits_and_limits():
 
 
 def test_copy_fed_gemm_eligibility():
-    """The copy-fed FP64 kernel is planned for the 256x128 tile (no split-K,
-    no COPY step) when every operand's stride-1 mode leads its row or
-    contracted group with an even extent and every other stride is even."""
+    """The copy-fed FP64 kernel is planned for the large tiles (256x128 and
+    128x256, no split-K; also after the copy of COPY+GEMM) when every operand's
+    stride-1 mode leads its row or contracted group with an even extent and
+    every other stride is even."""
     for la, lb, lc, ext in (synth.workload_cc_a(128, 32), synth.workload_cc_b(128, 32)):
         info = analyze(la, lb, lc, ext)
         assert info.tile_id == 11 and info.k_split == 1 and info.copy_fed == 1
     ext = {"a": 18, "b": 15, "c": 10, "d": 7, "i": 6, "j": 50}
     assert analyze("abcd", "cdij", "abij", ext, recipe="gemm", tile_id=11).copy_fed == 1
+    assert analyze("abcd", "cdij", "abij", ext, recipe="gemm", tile_id=12).copy_fed == 2
     assert analyze("abcd", "cdij", "abij", ext, recipe="gemm", tile_id=0).copy_fed == 0       # other tile
-    assert analyze("abcd", "cdij", "abij", ext, recipe="copy_gemm", tile_id=11).copy_fed == 0  # COPY step
+    assert analyze("abcd", "cdij", "abij", ext, recipe="copy_gemm", tile_id=11).copy_fed == 1  # after the COPY step
     assert analyze("abcd", "cdij", "abij", ext, precision="crt_int8").copy_fed == 0
     odd = dict(ext, a=17)                                       # odd leading extent of the row-fast operand
     assert analyze("abcd", "cdij", "abij", odd, recipe="gemm", tile_id=11).copy_fed == 0
@@ -319,6 +321,33 @@ def test_copy_fed_gemm_eligibility():
     # a strided (every other entry) view keeps no stride-1 mode: no 16-byte pairs
     sA = colmajor_strides([18, 15, 10, 7])
     assert analyze("abcd", "cdij", "abij", ext, sA=[2 * x for x in sA], recipe="gemm", tile_id=11).copy_fed == 0
+    # an explicit copy-fed tile overrides the tile's own shape
+    for name, code in tc.COPY_TILES.items():
+        assert analyze("abcd", "cdij", "abij", ext, recipe="gemm", tile_id=11, copy_tile=name).copy_fed == 1 + code
+    with pytest.raises(tc.TCError):
+        analyze("abcd", "cdij", "abij", ext, copy_tile=3)
+
+
+def test_copy_fed_tile_rule():
+    """Without a tile asked for, the copy-fed kernel takes the output tile
+    whose workgroups (one per compute unit of 256, dealt out in rounds) leave
+    the least output area in flight: the v=192, o=48 coupled-cluster shapes
+    (2304 x 36864 and 9216 x 9216 outputs) divide into exactly 9 rounds of
+    192 x 192 tiles, against 10.1 rounds of 256 x 128; the v=128, o=32 ones
+    (1024 x 16384, 4096 x 4096) into 2 rounds of 256 x 128."""
+    def rounds_area(M, N, bm, bn):
+        tiles = -(-M // bm) * -(-N // bn)
+        return -(-tiles // 256) * bm * bn
+
+    for (la, lb, lc, ext), want in ((synth.workload_cc_a(192, 48), 3), (synth.workload_cc_b(192, 48), 3),
+                                     (synth.workload_cc_a(128, 32), 1), (synth.workload_cc_b(128, 32), 1)):
+        info = analyze(la, lb, lc, ext)
+        assert info.copy_fed == want, (ext, info.copy_fed)
+        costs = [rounds_area(info.M, info.N, bm, bn) for bm, bn in ((256, 128), (128, 256), (192, 192))]
+        assert info.copy_fed == 1 + int(np.argmin(costs))
+    # a tile asked for keeps its own shape
+    la, lb, lc, ext = synth.workload_cc_a(192, 48)
+    assert analyze(la, lb, lc, ext, recipe="gemm", tile_id=11).copy_fed == 1
 
 
 def test_fast_division_method():
