@@ -214,6 +214,22 @@ tc_status tc_execute(tc_plan_t plan, const double* A, const double* B, double* C
                      double alpha, double beta, void* workspace, size_t workspace_bytes,
                      void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): tc_execute with the
+ * workspace taken from a fixed device array of TC_NOALLOC_SCRATCH_BYTES bytes
+ * (64 MiB) that the library holds on each device it runs on, from its load
+ * until the process ends.  The caller passes the plan, inputs, output, alpha,
+ * beta and stream exactly as for tc_execute; nothing is allocated or freed.
+ * Every call on one device shares that device's array and leaves its
+ * contents behind, so calls on one device whose executions overlap in time
+ * (several streams or host threads) race: serialise them.  Errors: those of
+ * tc_execute; TC_ERR_WORKSPACE, with nothing enqueued, for a plan whose
+ * info.workspace_bytes exceeds TC_NOALLOC_SCRATCH_BYTES; TC_ERR_HIP when the
+ * array's device address cannot be looked up (first call on a device). */
+#define TC_NOALLOC_SCRATCH_BYTES (64ll << 20)
+tc_status tc_execute_noalloc(tc_plan_t plan, const double* A, const double* B, double* C,
+                             double alpha, double beta, void* stream);
+
 /* Releases a plan from tc_plan_create and its device offset tables (Sec. 2.4:
  * the slicing loops the tables stand for).  NULL is accepted (TC_OK).  The
  * caller must make sure no enqueued tc_execute of the plan is still pending:

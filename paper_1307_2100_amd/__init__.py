@@ -93,6 +93,9 @@ _lib.tc_plan_query.restype = ctypes.c_int
 _lib.tc_execute.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
 _lib.tc_execute.restype = ctypes.c_int
+_lib.tc_execute_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+_lib.tc_execute_noalloc.restype = ctypes.c_int
 _lib.tc_plan_destroy.argtypes = [ctypes.c_void_p]
 _lib.tc_plan_destroy.restype = ctypes.c_int
 _lib.tc_permute.argtypes = [ctypes.c_int, _I64P, _I64P, _I64P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -158,6 +161,7 @@ _lib.tc_last_error.restype = ctypes.c_char_p
 _lib.tc_version.restype = ctypes.c_char_p
 
 EXPORTED = ["tc_options_default", "tc_analyze", "tc_suggest_layout", "tc_plan_create", "tc_plan_query", "tc_execute",
+            "tc_execute_noalloc",
             "tc_plan_destroy", "tc_permute", "tc_batch_create", "tc_batch_workspace", "tc_batch_execute",
             "tc_batch_set_options", "tc_batch_query", "tc_batch_autotune", "tc_batch_destroy",
             "tc_picker_candidate", "tc_picker_features", "tc_picker_install", "tc_picker_uninstall",
@@ -268,6 +272,14 @@ def tc_plan_query(plan):
 
 def tc_execute(plan, A_ptr, B_ptr, C_ptr, alpha, beta, ws_ptr, ws_bytes, stream):
     _check(_lib.tc_execute(plan, A_ptr, B_ptr, C_ptr, float(alpha), float(beta), ws_ptr, int(ws_bytes), stream))
+
+
+def tc_execute_noalloc(plan, A_ptr, B_ptr, C_ptr, alpha, beta, stream):
+    _check(_lib.tc_execute_noalloc(plan, A_ptr, B_ptr, C_ptr, float(alpha), float(beta), stream))
+
+
+# size of the library's fixed device workspace used by tc_execute_noalloc
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def tc_plan_destroy(plan):
@@ -382,6 +394,16 @@ class Plan:
         wbytes = ws.numel() * ws.element_size() if ws is not None else 0
         tc_execute(self.handle, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
                    ctypes.c_void_p(C.data_ptr()), alpha, beta, wptr, wbytes, _stream_handle(stream))
+        return C
+
+    def execute_noalloc(self, A, B, C, alpha=1.0, beta=0.0, stream=None):
+        """tc_execute_noalloc: like execute, with the library's fixed device
+        workspace in place of an allocated one."""
+        _require_f64_cuda(A, "A")
+        _require_f64_cuda(B, "B")
+        _require_f64_cuda(C, "C")
+        tc_execute_noalloc(self.handle, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                           ctypes.c_void_p(C.data_ptr()), alpha, beta, _stream_handle(stream))
         return C
 
     def autotune(self, A, B, C, stream=None):

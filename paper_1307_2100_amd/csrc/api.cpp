@@ -603,6 +603,10 @@ struct tc_batch_s {
   }
 };
 
+namespace tc {
+tc_status set_error(tc_status s, const char* msg) { return fail(s, msg ? msg : ""); }
+}  // namespace tc
+
 extern "C" {
 
 void tc_options_default(tc_options* opt) {

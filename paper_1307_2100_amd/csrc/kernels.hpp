@@ -35,6 +35,9 @@ namespace tc {
 
 constexpr int kMaxRank = 16;
 
+// Records `msg` as the calling thread's tc_last_error() text and returns s
+// (for entry points defined outside the main ABI source).
+tc_status set_error(tc_status s, const char* msg);
 
 // Offsets of one operand along one index group: a table of per-index
 // offsets, or (tab == nullptr) an affine map idx * stride.
