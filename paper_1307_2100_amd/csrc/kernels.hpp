@@ -281,7 +281,7 @@ constexpr CrtTileCfg kCrtTiles[] = {TC_CRT_TILES(TC_CRT_ROW)};
 #undef TC_CRT_ROW
 constexpr int kCrtNumTiles = sizeof(kCrtTiles) / sizeof(kCrtTiles[0]);
 static_assert(kCrtNumTiles == TC_CRT_NUM_TILES, "tile table and header agree");
-constexpr int kCrtDefaultTile = 8;
+constexpr int kCrtDefaultTile = 11;
 constexpr int kCrtBK = 64;
 // Largest b <= 48 such that n moduli represent every sum of K products of
 // integers |a|, |b| <= 2^b without ambiguity: 2 K 4^b < P, P the product of

@@ -869,6 +869,137 @@ __global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_dma_kernel(CrtGemmArg
   crt_store_residues<TM, TN, WM, WN>(g, acc, mod, p, m0 + wm * WM, n0 + wn * WN, lane);
 }
 
+// The copy-fed residue product for 8 wavefronts (each 64 x 128 or 128 x 64
+// of the tile) with the schedule pipelined: the fragments of k-step ks + 1
+// are read from LDS between the MFMAs of k-step ks (two register sets
+// alternating), and the copies of k-step ks + NS - 1 are spread between them
+// too, so the matrix cores are not left idle while reads and copies issue.
+// One barrier per k-step, before its MFMAs: after it k-step ks + 1 is visible
+// to every wavefront (each first waits for its own copies of it: at most the
+// CPW (NS - 3) copies issued after them outstanding) and the stage of k-step
+// ks - 1 -- whose fragments were all read during k-step ks - 2 and consumed
+// by the MFMAs of k-step ks - 1 -- is free for the copies issued after it.
+// Copies past the last k-step repeat it into that freed stage.
+template <int BM, int BN, int WGM, int WGN, int NS>
+__global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_pipe_kernel(CrtGemmArgs g) {
+  constexpr int BK = kCrtBK;
+  constexpr int NW = WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int STAGE = (BM + BN) * BK;          // bytes per stage
+  constexpr int CH = (BM + BN) / 16;             // 1 KB copies per stage
+  static_assert(CH % NW == 0 && BM % 16 == 0, "whole copies per wavefront, none straddling A and B");
+  constexpr int CPW = CH / NW;                   // copies per wavefront per k-step
+  static_assert(NS >= 3 && CPW * (NS - 2) <= 15, "ring of three or more stages; wait count fits the vmcnt field");
+  constexpr int NM = TM * TN, NR = TM + TN;
+  extern __shared__ __attribute__((aligned(16))) signed char dsm[];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  int mod, p;
+  int64_t m0, n0;
+  crt_tile_of(g, BM, BN, &mod, &p, &m0, &n0);
+  const signed char* const PA = g.pa + (int64_t)mod * g.Mp * g.Kp + m0 * BK;
+  const signed char* const PB = g.pb + (int64_t)mod * g.Np * g.Kp + n0 * BK;
+  const int64_t kstepA = g.Mp * BK, kstepB = g.Np * BK;
+  // this lane's source address of each of its copies at k-step 0 (rows 16c .. 16c+15, chunk lane/16)
+  const signed char* base[CPW];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int c = wave + NW * j;
+    const int r = 16 * c + (lane & 15);
+    base[j] = (16 * c < BM ? PA + r * BK : PB + (r - BM) * BK) + (lane >> 4) * 16;
+  }
+  auto copy1 = [&](int j, int64_t ks, int stage) {
+    const int c = wave + NW * j;
+    const int64_t off = 16 * c < BM ? ks * kstepA : ks * kstepB;
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(base[j] + off),
+                                     (void __attribute__((address_space(3)))*)(dsm + stage * STAGE + c * 1024), 16,
+                                     0, 0);
+  };
+  // fragment-order offsets: row group base b, lane l at 64 b + 16 l
+  const int a_lds = (wm * WM) * BK + lane * 16, b_lds = (BM + wn * WN) * BK + lane * 16;
+  i4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = i4{0, 0, 0, 0};
+  // every residue product is at most 2^14 in magnitude: reducing the sums
+  // modulo p every 2^16 contracted indices keeps them below 2^31
+  constexpr int64_t kReduce = 65536 / BK;
+  static_assert(kReduce % 2 == 0, "the loop takes k-steps in pairs");
+  const int64_t ksteps = g.Kp / BK, last = ksteps - 1;
+#pragma unroll
+  for (int s = 0; s < NS - 1; ++s)
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) copy1(j, s < last ? s : last, s);
+  __builtin_amdgcn_s_waitcnt((CPW * (NS - 2)) | (7 << 4) | (15 << 8));  // this wavefront's copies of k-step 0
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+  i4 fa0[TM], fb0[TN], fa1[TM], fb1[TN];
+#pragma unroll
+  for (int q = 0; q < TM; ++q) fa0[q] = *(const i4*)(dsm + a_lds + q * 16 * BK);
+#pragma unroll
+  for (int q = 0; q < TN; ++q) fb0[q] = *(const i4*)(dsm + b_lds + q * 16 * BK);
+  int st = 0;  // stage of k-step ks
+  // k-step ks on (fa, fb); reads k-step ks + 1 into (ga, gb)
+  auto body = [&](int64_t ks, const i4 (&fa)[TM], const i4 (&fb)[TN], i4 (&ga)[TM], i4 (&gb)[TN]) {
+    __builtin_amdgcn_s_waitcnt((CPW * (NS - 3)) | (7 << 4) | (15 << 8));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t nk = ks + NS - 1;
+    const int cs = (st + NS - 1) % NS, rs = (st + 1) % NS;
+    const signed char* nx = dsm + rs * STAGE;
+    constexpr int SPAN = (2 * NM) / 3;  // reads in the first two thirds of the MFMAs
+#pragma unroll
+    for (int q = 0; q < NM; ++q) {
+      acc[q / TN][q % TN] =
+          __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[q / TN], fb[q % TN], acc[q / TN][q % TN], 0, 0, 0);
+      const bool r = q < SPAN && q * NR / SPAN != (q + 1) * NR / SPAN;
+      const bool c = q * CPW / NM != (q + 1) * CPW / NM;
+      if (r || c) __builtin_amdgcn_sched_barrier(0);
+      if (r) {
+        const int x = q * NR / SPAN;
+        if (x < TM)
+          ga[x] = *(const i4*)(nx + a_lds + x * 16 * BK);
+        else
+          gb[x - TM] = *(const i4*)(nx + b_lds + (x - TM) * 16 * BK);
+      }
+      if (c) copy1(q * CPW / NM, nk < last ? nk : last, cs);
+      if (r || c) __builtin_amdgcn_sched_barrier(0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    st = rs;
+  };
+  int64_t ks = 0;
+  for (; ks + 1 < last; ks += 2) {
+    body(ks, fa0, fb0, fa1, fb1);
+    body(ks + 1, fa1, fb1, fa0, fb0);
+    if ((ks + 2) % kReduce == 0) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] %= p;
+    }
+  }
+  if (ks < last) {  // one k-step left before the last
+    body(ks, fa0, fb0, fa1, fb1);
+#pragma unroll
+    for (int q = 0; q < TM; ++q) fa0[q] = fa1[q];
+#pragma unroll
+    for (int q = 0; q < TN; ++q) fb0[q] = fb1[q];
+  }
+#pragma unroll
+  for (int q = 0; q < NM; ++q)
+    acc[q / TN][q % TN] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa0[q / TN], fb0[q % TN], acc[q / TN][q % TN], 0, 0, 0);
+  // the repeated copies of the tail must land before the workgroup's LDS is released
+  __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
+  crt_store_residues<TM, TN, WM, WN>(g, acc, mod, p, m0 + wm * WM, n0 + wn * WN, lane);
+}
+
 // Chinese-remainder rebuild: with M_i = P / p_i and w_i = M_i (M_i^-1 mod p_i)
 // (each below P), Z = sum_i z_i w_i mod P, taken in (-P/2, P/2].  P < 2^111,
 // so the sum of at most 14 terms below 2^8 P fits in 128 bits.
@@ -951,9 +1082,18 @@ hipError_t launch_crt_gemm(const CrtGemmArgs& g, unsigned blocks, hipStream_t s)
   } else {
     constexpr int bytes = PF * (BM + BN) * kCrtBK;
     static std::atomic<uint64_t> allowed{0};
-    const hipError_t e = allow_dynamic_lds((const void*)crt_gemm_dma_kernel<BM, BN, WGM, WGN, PF>, bytes, allowed);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((crt_gemm_dma_kernel<BM, BN, WGM, WGN, PF>), dim3(blocks), dim3(64 * WGM * WGN), bytes, s, g);
+    if constexpr (WGM * WGN == 8) {  // registers for two fragment sets: the pipelined schedule
+      const hipError_t e =
+          allow_dynamic_lds((const void*)crt_gemm_pipe_kernel<BM, BN, WGM, WGN, PF>, bytes, allowed);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((crt_gemm_pipe_kernel<BM, BN, WGM, WGN, PF>), dim3(blocks), dim3(64 * WGM * WGN), bytes, s,
+                         g);
+    } else {
+      const hipError_t e = allow_dynamic_lds((const void*)crt_gemm_dma_kernel<BM, BN, WGM, WGN, PF>, bytes, allowed);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((crt_gemm_dma_kernel<BM, BN, WGM, WGN, PF>), dim3(blocks), dim3(64 * WGM * WGN), bytes, s,
+                         g);
+    }
   }
   return hipGetLastError();
 }
