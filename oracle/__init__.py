@@ -31,8 +31,9 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        path = build_oracle.OUT
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(build_oracle.SRC):
+        path = os.environ.get("TC_ORACLE_LIBRARY") or build_oracle.OUT
+        if path == build_oracle.OUT and (not os.path.exists(path) or
+                                         os.path.getmtime(path) < os.path.getmtime(build_oracle.SRC)):
             build_oracle.build(force=True)
         lib = ctypes.CDLL(path)
         i64p = ctypes.POINTER(ctypes.c_int64)

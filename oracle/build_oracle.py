@@ -10,6 +10,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tc_oracle.c")
 OUT_DIR = os.path.join(HERE, "_build")
 OUT = os.path.join(OUT_DIR, "libtc_oracle.so")
+# AddressSanitizer + UndefinedBehaviorSanitizer build (clang, whose runtime the
+# sanitized library run preloads), selected through TC_ORACLE_LIBRARY
+OUT_SANITIZED = os.path.join(OUT_DIR, "libtc_oracle_sanitized.so")
+CLANG = "/opt/rocm/llvm/bin/clang"
 
 
 def build(force: bool = True) -> str:
@@ -22,6 +26,17 @@ def build(force: bool = True) -> str:
     subprocess.check_call(cmd)
     os.replace(tmp, OUT)
     return OUT
+
+
+def build_sanitized() -> str:
+    os.makedirs(OUT_DIR, exist_ok=True)
+    tmp = OUT_SANITIZED + ".tmp%d" % os.getpid()
+    cmd = [CLANG, "-O1", "-g", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+           SRC, "-o", tmp, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, OUT_SANITIZED)
+    return OUT_SANITIZED
 
 
 if __name__ == "__main__":

@@ -13,7 +13,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_lib", "libtc.so")
+# TC_LIBRARY names another build of the same sources (the host-sanitized one
+# that tests/run_sanitized.py loads); by default the in-tree libtc.so.
+LIB_PATH = os.environ.get("TC_LIBRARY") or os.path.join(HERE, "_lib", "libtc.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libtc.so is not built (%s); run paper_1307_2100_amd.build.build()" % LIB_PATH)

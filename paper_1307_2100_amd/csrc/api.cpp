@@ -55,7 +55,21 @@ tc_status analyze_args(int ra, const int64_t* ea, const int64_t* sa, const int32
   if ((s = fill_desc(&C, rc, ec, sc, lc, "C")) != TC_OK) return s;
   tc_options o;
   tc_options_default(&o);
-  if (opt) o = *opt;
+  if (opt) {
+    // A C caller may store any integer in the enum fields: check them as
+    // plain ints before any is read as its enum type
+    static_assert(sizeof(tc_precision) == sizeof(int) && sizeof(tc_recipe) == sizeof(int) &&
+                      sizeof(tc_picker) == sizeof(int),
+                  "enum fields of tc_options are int-sized");
+    int prec, rec, pick;
+    std::memcpy(&prec, &opt->precision, sizeof(int));
+    std::memcpy(&rec, &opt->recipe, sizeof(int));
+    std::memcpy(&pick, &opt->picker, sizeof(int));
+    if (prec < TC_PREC_F64 || prec > TC_PREC_F64_CRT_INT8 || rec < TC_RECIPE_AUTO || rec > TC_RECIPE_DOT ||
+        pick < TC_PICKER_RULES || pick > TC_PICKER_TUNED)
+      return fail(TC_ERR_INVALID_ARG, "invalid tc_options field");
+    o = *opt;
+  }
   std::string err;
   s = tc::analyze(A, B, C, o, an, &err);
   if (s != TC_OK) return fail(s, err);

@@ -143,6 +143,12 @@ def test_extent_overlap_rank_errors():
     with pytest.raises(tc.TCError) as e:
         analyze("ik", "kj", "ij", {"i": 2, "k": 2, "j": 2}, recipe=9)
     assert e.value.status == tc.TC_ERR_INVALID_ARG
+    # every enum field is checked as a plain int at the ABI (a C caller may store
+    # any value there; reading it as the enum type first would be undefined)
+    for bad in (dict(precision=4), dict(precision=-1), dict(recipe=-3), dict(picker=3), dict(picker=1 << 20)):
+        with pytest.raises(tc.TCError) as e:
+            analyze("ik", "kj", "ij", {"i": 2, "k": 2, "j": 2}, **bad)
+        assert e.value.status == tc.TC_ERR_INVALID_ARG, bad
 
 
 def test_execute_rejects_null_plan_and_small_workspace_without_gpu():
