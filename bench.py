@@ -494,13 +494,14 @@ def batch_runs(n_random=2000, reps=10):
 
 def timing_modes_runs(reps=10, graph_reps=20):
     """The small 3-D contraction C[i,j,m] = A[i,k,m] B[k,j] (extents 64) and
-    the two grid contractions, each timed three ways with HIP events on the
-    current stream: warm (median of reps back-to-back-launched calls, each
-    bracketed by its own events), cold (a 1 GiB buffer is written before
-    each call, which evicts the 256 MB last-level cache; the call alone is
-    timed) and graph replay (the call captured once in a HIP graph, mean
-    over graph_reps replays).  Every replay's output is compared with the
-    eager result."""
+    the two grid contractions, timed with HIP events on the current stream:
+    warm (median of reps calls, each bracketed by its own events), cold (a
+    1 GiB buffer is written before each call, which evicts the 256 MB
+    last-level cache; the call alone is timed), device time of one eager call
+    and of one replay of the call captured in a HIP graph (the stream kept
+    busy before each, so the events time execution rather than submission),
+    and the per-call time of graph_reps back-to-back replays.  Every replay's
+    output is compared with the eager result."""
     import numpy as np
     import torch
 
@@ -553,6 +554,23 @@ def timing_modes_runs(reps=10, graph_reps=20):
             g.replay()
             torch.cuda.synchronize()
             mismatch = max(mismatch, float((C - eager).abs().max()))
+        # device time of one call: the stream is first kept busy by a sleep
+        # kernel (about 0.2 ms), so the call is already queued when its start
+        # event fires and the events bracket its execution, not its submission
+        def device_ms(fn):
+            ts = []
+            for _ in range(reps):
+                torch.cuda._sleep(500000)
+                d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                d0.record(stream)
+                fn()
+                d1.record(stream)
+                torch.cuda.synchronize()
+                ts.append(d0.elapsed_time(d1))
+            return float(np.median(ts))
+        eager_dev = device_ms(run)
+        graph_dev = device_ms(g.replay)
+        # back-to-back replays: per-call time when the host submits them in a row
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(graph_reps):
@@ -560,12 +578,15 @@ def timing_modes_runs(reps=10, graph_reps=20):
         e1.record(stream)
         torch.cuda.synchronize()
         info = plan.info
-        print("[bench] %s: warm %.4f ms, cold %.4f ms, graph replay %.4f ms" % (
-            name, float(np.median(warm)), float(np.median(cold)), e0.elapsed_time(e1) / graph_reps),
-            file=sys.stderr, flush=True)
+        print("[bench] %s: warm %.4f ms, cold %.4f ms, device time eager %.4f ms, graph replay %.4f ms, "
+              "back-to-back replays %.4f ms each" % (name, float(np.median(warm)), float(np.median(cold)), eager_dev,
+                                                    graph_dev, e0.elapsed_time(e1) / graph_reps),
+              file=sys.stderr, flush=True)
         out[name] = {"warm_ms_median": round(float(np.median(warm)), 4),
                      "cold_ms_median": round(float(np.median(cold)), 4),
-                     "graph_replay_ms": round(e0.elapsed_time(e1) / graph_reps, 4),
+                     "device_ms_eager_median": round(eager_dev, 4),
+                     "device_ms_graph_replay_median": round(graph_dev, 4),
+                     "back_to_back_graph_replay_ms": round(e0.elapsed_time(e1) / graph_reps, 4),
                      "graph_replay_max_abs_diff_vs_eager": mismatch,
                      "kernel": tc.KERNEL_NAMES[info.kernel], "flops": info.flops, "bytes": info.bytes}
         del g

@@ -285,8 +285,10 @@ def slicing_workloads(quick):
 
 def workloads(quick):
     sq = (64, 128, 256) if quick else (64, 128, 192, 256, 384, 512)
-    cc_ij = (500, 1000) if quick else (500, 1000, 2000)
-    cc_f = (30, 45) if quick else (30, 45, 60)
+    # Fig. 4D-1: i = j up to 3000 at free extents 30, and free extents 30 to
+    # 100 at i = j = 1000 (the largest input, Y, is 65 GB and 80 GB there)
+    cc_ij = (500, 1000) if quick else (500, 1000, 2000, 3000)
+    cc_f = (30, 45) if quick else (30, 45, 60, 80, 100)
     gr_f = (100, 200) if quick else (100, 200, 400, 600)
     for n in sq:
         yield "square", "abg", "hbg", "ah", {l: n for l in "abgh"}
@@ -313,7 +315,10 @@ def markdown(rows, cmd):
              "Command: `%s`" % cmd, "",
              "Inputs: seeded uniform[-1,1] FP64 drawn on the device, column-major in the listed label order. "
              "Times: HIP events on the current stream, mean over the calls shown (one untimed call first). "
-             "`auto` is the rules' choice; every forced recipe agrees with it to < 1e-12 K.", ""]
+             "`auto` is the rules' choice; every forced recipe agrees with it to < 1e-12 K. Each cell gives "
+             "GFLOP/s and, in brackets, the fraction of the contraction's roofline bound: max(2 M N K L / "
+             "78.6 TFLOP/s, 8 (|A| + |B| + |C|) / 8 TB/s) over the measured time (the COPY of COPY+GEMM is "
+             "not counted as work).", ""]
     for study, title in (("square", "Sec. 4.1: 3-D square tensors"),
                          ("cc", "Sec. 4.2 example 1: coupled-cluster shapes (short free, long contracted)"),
                          ("gr", "Sec. 4.2 example 2: general-relativity shapes (contracted extents 4)")):
@@ -341,6 +346,8 @@ def markdown(rows, cmd):
                     cells.append("-")
                     continue
                 txt = "%.0f" % r["gflops"] if r["gflops"] >= 10 else "%.2f" % r["gflops"]
+                if r.get("frac_roofline") is not None:
+                    txt += " [%.2f]" % r["frac_roofline"]
                 if rc == "auto":
                     txt += " (%s)" % r["ran"]
                 cells.append(txt)
