@@ -113,10 +113,34 @@ def features(shape):
 
 
 # ----------------------------------------------------------------- collection
-def collect(out, n, seed=0, log_every=200):
+# The sources the candidates run through (planner, FP64 execution path and
+# its kernels, the C header); batches, split precision and the network are
+# not among them.
+CANDIDATE_SOURCES = ("api.cpp", "planner.cpp", "planner.hpp", "kernels.hpp", "gett_f64.hip", "gett_tile.hpp",
+                     "permute.hip", "blas2.hip", "lanes.hpp", "batched.hip", "batched_slab.hpp")
+
+
+def library_source_sha():
+    """sha256 (first 16 hex digits) of CANDIDATE_SOURCES and the C header:
+    the kernels and rules that candidate timings were taken with."""
+    import hashlib
+    root = os.path.dirname(HERE)
+    paths = [os.path.join(HERE, "csrc", f) for f in CANDIDATE_SOURCES]
+    paths.append(os.path.join(root, "include", "tc.h"))
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def collect(out, n, seed=0, log_every=200, seconds=None):
     """Times every candidate on n random shapes (index i uses seed + i) and
-    appends one JSON line per shape to `out`; an existing file is resumed."""
+    appends one JSON line per shape to `out`; an existing file is resumed.
+    With `seconds`, stops after the first shape that ends past that budget
+    (run again to continue)."""
     import torch
+    lib_sha = library_source_sha()
     done = 0
     if os.path.exists(out):
         with open(out) as f:
@@ -138,11 +162,15 @@ def collect(out, n, seed=0, log_every=200):
             info = plan.info
             plan.close()
             rec = {"i": i, "seed": seed, "shape": shape, "features": feat, "rule_candidate": rc, "ms": ms,
-                   "best": best, "flops": info.flops, "bytes": info.bytes, "paper_class": info.paper_class}
+                   "best": best, "flops": info.flops, "bytes": info.bytes, "paper_class": info.paper_class,
+                   "lib_sha": lib_sha}
             f.write(json.dumps(rec) + "\n")
             if (i + 1) % log_every == 0:
                 f.flush()
                 print("collect: %d/%d shapes, %.1f s" % (i + 1, n, time.time() - t0), flush=True)
+            if seconds is not None and time.time() - t0 > seconds:
+                print("collect: time budget spent after %d/%d shapes; run again to resume" % (i + 1, n), flush=True)
+                return
     print("collect: done, %d shapes in %s" % (n, out), flush=True)
 
 
@@ -353,6 +381,7 @@ def main(argv=None):
     c.add_argument("--out", required=True)
     c.add_argument("--n", type=int, required=True)
     c.add_argument("--seed", type=int, default=0)
+    c.add_argument("--seconds", type=float, default=None, help="stop after this many seconds (resumable)")
     t = sub.add_parser("train")
     t.add_argument("--data", nargs="+", required=True)
     t.add_argument("--test", type=int, default=5000)
@@ -371,7 +400,7 @@ def main(argv=None):
         print(json.dumps({"heldout": rules_now(te), "train": rules_now(tr)}), flush=True)
         return
     if a.cmd == "collect":
-        collect(a.out, a.n, a.seed)
+        collect(a.out, a.n, a.seed, seconds=a.seconds)
     elif a.cmd == "train":
         recs = load_records(a.data)
         tr, te = _split(recs, a.test)
@@ -383,8 +412,10 @@ def main(argv=None):
         Xte, mste = arrays(te)
         res_te = evaluate(predict(params, mean, std, Xte), mste) if len(te) else {}
         res_tr = evaluate(predict(params, mean, std, Xtr), mstr)
+        shas = sorted({r.get("lib_sha", "unrecorded") for r in recs})
         meta = {"train_shapes": len(tr), "test_shapes": len(te), "epochs": a.epochs, "train_seconds": secs,
-                "final_train_loss": hist[-1], "eval_heldout": res_te, "eval_train": res_tr}
+                "final_train_loss": hist[-1], "eval_heldout": res_te, "eval_train": res_tr,
+                "timings_library_source_sha": shas, "trained_with_library_source_sha": library_source_sha()}
         save_model(a.out, params, mean, std, meta)
         print(json.dumps({"heldout": res_te, "train": {k: res_tr[k] for k in res_tr if "histogram" not in k}}),
               flush=True)
