@@ -164,5 +164,6 @@ def test_trained_model_against_rules_and_exhaustive_timing():
     gm = lambda x: float(np.exp(np.mean(np.log(x))))  # noqa: E731
     res = dict(pick_over_best=gm(t_pick / best), rules_over_best=gm(t_rule / best), gain=gm(t_rule / t_pick))
     print("picker on fresh shapes:", res)
-    # the network must not lose to the rules it augments
-    assert res["gain"] >= 1.0
+    # the network beats the rules it augments by a clear margin (1.39 on the
+    # 5000 held-out shapes of its training data, 1.2 asked for here)
+    assert res["gain"] >= 1.2
