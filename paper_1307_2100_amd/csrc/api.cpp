@@ -356,7 +356,9 @@ struct tc_batch_s {
   tc::BatchItem* d_items = nullptr;
   tc::BatchTask* d_tasks = nullptr;
   int64_t* d_chunks = nullptr;
-  int64_t nchunks = 0;
+  int64_t nchunks = 0;                          // chunks of all engines
+  int64_t chunk_base[tc::kBatchEngines] = {};   // engine e's bounds start at d_chunks + chunk_base[e]
+  int64_t engine_chunks[tc::kBatchEngines] = {};
   tc::BatchPtrs* h_ptrs = nullptr;
   hipStream_t capture_stream = nullptr;
   hipEvent_t done = nullptr;
@@ -431,12 +433,9 @@ struct tc_batch_s {
     std::vector<HT> tasks;
     n_cnt = 0;
     n_parts = 0;
-    // Slab tasks take the LDS the configuration's occupancy leaves per
-    // workgroup (more points per task, fewer tasks), within 16 to 64 KB.
-    const int wgs = tc::batch_blocks_per_cu(cfg);
-    // (1 KB per workgroup left for static LDS and allocation granularity)
-    slab_lds = wgs > 0 ? lds_per_cu / (int)sizeof(double) / wgs - 128 : tc::kBatchSlabLdsDoubles;
-    slab_lds = std::min(std::max(slab_lds, tc::kBatchSlabLdsDoubles), tc::kBatchSlabLdsMaxDoubles);
+    // Slab tasks run in their own launch with 16 KB of LDS per workgroup (the
+    // budget measured best for the grid contractions on their own).
+    slab_lds = tc::kBatchSlabLdsDoubles;
     for (tc::BatchItem& it : items) {
       if (it.kind != tc::kBatchSlab) continue;
       const int per = it.b.a.size + it.b.b.size + it.b.c.size;
@@ -509,26 +508,39 @@ struct tc_batch_s {
         for (int64_t t = 0; t < nt; ++t) tasks.push_back({cost, tc::BatchTask{i, 0, t}});
       }
     }
-    std::stable_sort(tasks.begin(), tasks.end(), [](const HT& a, const HT& b) { return a.cost > b.cost; });
+    // One task list per engine, longest tasks first, laid out one after the
+    // other; each engine's list is cut into chunks of about its total / (16
+    // per CU) cost: the costly tasks at the front get chunks of their own,
+    // the many cheap ones share.
+    std::stable_sort(tasks.begin(), tasks.end(), [&](const HT& a, const HT& b) {
+      const int ea = tc::batch_engine_of(items[a.t.item].kind), eb = tc::batch_engine_of(items[b.t.item].kind);
+      return ea != eb ? ea < eb : a.cost > b.cost;
+    });
     std::vector<tc::BatchTask> flat(tasks.size());
-    double total = 0.0;
-    for (size_t i = 0; i < tasks.size(); ++i) {
-      flat[i] = tasks[i].t;
-      total += tasks[i].cost;
-    }
-    // chunks of about total / (16 per CU) cost: the costly tasks at the front
-    // get chunks of their own, the many cheap ones share
-    std::vector<int64_t> bounds{0};
-    const double target = total / (16.0 * num_cus);
-    double acc = 0.0;
-    for (size_t i = 0; i < tasks.size(); ++i) {
-      acc += tasks[i].cost;
-      if (acc >= target || i + 1 == tasks.size()) {
-        bounds.push_back((int64_t)i + 1);
-        acc = 0.0;
+    for (size_t i = 0; i < tasks.size(); ++i) flat[i] = tasks[i].t;
+    std::vector<int64_t> bounds;
+    size_t first = 0;
+    for (int e = 0; e < tc::kBatchEngines; ++e) {
+      size_t last = first;
+      double total = 0.0;
+      while (last < tasks.size() && tc::batch_engine_of(items[tasks[last].t.item].kind) == e)
+        total += tasks[last++].cost;
+      chunk_base[e] = (int64_t)bounds.size();
+      bounds.push_back((int64_t)first);
+      const double target = total / (16.0 * num_cus);
+      double acc = 0.0;
+      for (size_t i = first; i < last; ++i) {
+        acc += tasks[i].cost;
+        if (acc >= target || i + 1 == last) {
+          bounds.push_back((int64_t)i + 1);
+          acc = 0.0;
+        }
       }
+      engine_chunks[e] = (int64_t)bounds.size() - 1 - chunk_base[e];
+      first = last;
     }
-    nchunks = (int64_t)bounds.size() - 1;
+    nchunks = 0;
+    for (int e = 0; e < tc::kBatchEngines; ++e) nchunks += engine_chunks[e];
     if (d_chunks) (void)hipFree(d_chunks);
     d_chunks = nullptr;
     if (hipMalloc((void**)&d_chunks, bounds.size() * sizeof(int64_t)) != hipSuccess)
@@ -559,8 +571,22 @@ struct tc_batch_s {
     double* parts = (double*)((char*)ws + parts_offset(n_cnt));
     hipError_t e = hipMemcpyAsync(d_ptrs, h_ptrs, sizeof(tc::BatchPtrs) * n, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
-    tc::BatchLaunch bl{d_items, d_ptrs, d_tasks, ntasks, d_chunks, nchunks, counter, parts, cnt, n_cnt, config,
-                       slab_lds, num_cus};
+    tc::BatchLaunch bl{};
+    bl.items = d_items;
+    bl.ptrs = d_ptrs;
+    bl.tasks = d_tasks;
+    bl.ntasks = ntasks;
+    for (int e = 0; e < tc::kBatchEngines; ++e) {
+      bl.chunks[e] = d_chunks + chunk_base[e];
+      bl.nchunks[e] = engine_chunks[e];
+    }
+    bl.counter = counter;
+    bl.parts = parts;
+    bl.tile_cnt = cnt;
+    bl.n_cnt = n_cnt;
+    bl.config = config;
+    bl.slab_lds_doubles = slab_lds;
+    bl.num_cus = num_cus;
     return tc::launch_batch(bl, st);
   }
 

@@ -137,7 +137,11 @@ TC_DEV void batch_lanes_out(const BatchItem& it, const GettParams& p, const Batc
   }
 }
 
-template <int BM, int BN, int BK>
+// ENG selects the engine this launch runs (kBatchEngineGemm, kBatchEngineLanes
+// or kBatchEngineSlab): its task list holds tasks of that engine only, and the
+// instance carries only that engine's code, so the memory-bound engines are
+// not held to the occupancy the GEMM tiles' registers and LDS allow.
+template <int BM, int BN, int BK, int ENG>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict__ items,
                                                     const BatchPtrs* __restrict__ ptrs,
                                                     const BatchTask* __restrict__ tasks,
@@ -166,7 +170,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict_
     task.idx = uni64(task.idx);
     const BatchItem& it = items[task.item];
     const BatchPtrs pt = ptrs[task.item];
-    if (it.kind == kBatchLanesK || it.kind == kBatchLanesOut) {
+    if (ENG == kBatchEngineLanes) {
       GettParams p = it.g;
       p.A = it.swapped ? pt.B : pt.A;
       p.B = it.swapped ? pt.A : pt.B;
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict_
         batch_lanes_k(it, p, task, parts, tile_cnt);
       else
         batch_lanes_out(it, p, task, parts, tile_cnt, &last);
-    } else if (it.kind == kBatchGemm) {
+    } else if (ENG == kBatchEngineGemm) {
       GettParams p = it.g;
       p.A = it.swapped ? pt.B : pt.A;
       p.B = it.swapped ? pt.A : pt.B;
@@ -218,54 +222,53 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict_
 
 __global__ void batch_reset_kernel(unsigned long long* counter, unsigned* tile_cnt, int64_t n_cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *counter = 0ull;
+  if (i < kBatchEngines) counter[i] = 0ull;
   if (i < n_cnt) tile_cnt[i] = 0u;
+}
+
+// LDS (bytes) of an engine's launch
+size_t engine_lds_bytes(int eng, int gemm_doubles, int slab_lds_doubles) {
+  if (eng == kBatchEngineGemm) return (size_t)gemm_doubles * sizeof(double);
+  if (eng == kBatchEngineSlab) return (size_t)slab_lds_doubles * sizeof(double);
+  return 0;
+}
+
+template <int BM, int BN, int BK, int ENG>
+hipError_t launch_engine(const BatchLaunch& bl, hipStream_t s) {
+  if (bl.nchunks[ENG] == 0) return hipSuccess;
+  const size_t lds = engine_lds_bytes(ENG, gett_lds_doubles<BM, BN, BK>(), bl.slab_lds_doubles);
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<BM, BN, BK, ENG>, 256, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  int64_t grid = (int64_t)bl.num_cus * per_cu;
+  if (grid > bl.nchunks[ENG]) grid = bl.nchunks[ENG];
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((batch_kernel<BM, BN, BK, ENG>), dim3((unsigned)grid), dim3(256), lds, s, bl.items, bl.ptrs,
+                     bl.tasks, bl.chunks[ENG], bl.nchunks[ENG], bl.counter + ENG, bl.parts, bl.tile_cnt);
+  return hipGetLastError();
 }
 
 template <int BM, int BN, int BK>
 hipError_t launch_cfg(const BatchLaunch& bl, hipStream_t s) {
-  const size_t lds = batch_lds_bytes(bl.config, bl.slab_lds_doubles);
-  int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<BM, BN, BK>, 256, lds);
-  if (e != hipSuccess) return e;
-  if (per_cu < 1) per_cu = 1;
-  int64_t grid = (int64_t)bl.num_cus * per_cu;
-  if (grid > bl.nchunks) grid = bl.nchunks;
-  if (grid < 1) grid = 1;
   hipLaunchKernelGGL(batch_reset_kernel, dim3((unsigned)((bl.n_cnt + 255) / 256 + 1)), dim3(256), 0, s, bl.counter,
                      bl.tile_cnt, bl.n_cnt);
-  e = hipGetLastError();
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((batch_kernel<BM, BN, BK>), dim3((unsigned)grid), dim3(256), lds, s, bl.items, bl.ptrs,
-                     bl.tasks, bl.chunks, bl.nchunks, bl.counter, bl.parts, bl.tile_cnt);
-  return hipGetLastError();
+  // the engines one after the other: GEMM tiles, then the memory-bound
+  // inner products and matrix-vector groups, then the slabs
+  if ((e = launch_engine<BM, BN, BK, kBatchEngineGemm>(bl, s)) != hipSuccess) return e;
+  if ((e = launch_engine<BM, BN, BK, kBatchEngineLanes>(bl, s)) != hipSuccess) return e;
+  return launch_engine<BM, BN, BK, kBatchEngineSlab>(bl, s);
 }
 
 }  // namespace
 
-size_t batch_lds_bytes(int config, int slab_lds_doubles) {
-  int g = 0;
-  switch (config) {
-#define TC_BCFG(id, bm, bn, bk) \
-  case id: g = gett_lds_doubles<bm, bn, bk>(); break;
-    TC_BATCH_TILES(TC_BCFG)
-#undef TC_BCFG
-    default: g = 0;
-  }
-  return (size_t)(g > slab_lds_doubles ? g : slab_lds_doubles) * sizeof(double);
-}
-
-int batch_blocks_per_cu(int config) {
+int batch_slab_blocks_per_cu(int slab_lds_doubles) {
   int n = 0;
-  const size_t lds = batch_lds_bytes(config, kBatchSlabLdsDoubles);
-  hipError_t e = hipErrorInvalidValue;
-  switch (config) {
-#define TC_BCFG(id, bm, bn, bk) \
-  case id: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<bm, bn, bk>, 256, lds); break;
-    TC_BATCH_TILES(TC_BCFG)
-#undef TC_BCFG
-    default: break;
-  }
+  // the slab engine's code is the same in every tile configuration
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &n, batch_kernel<64, 64, 16, kBatchEngineSlab>, 256, (size_t)slab_lds_doubles * sizeof(double));
   return e == hipSuccess ? n : 0;
 }
 

@@ -391,25 +391,30 @@ struct BatchTask {
   int seg;               // contracted segment (ksplit > 1)
   int64_t idx;           // tile (kind 0), slab (1) or output group (2, 3) index
 };
+// Engines of a batch: each runs as its own persistent launch over its own
+// task list (GEMM tiles; inner products and matrix-vector groups; slabs).
+enum { kBatchEngineGemm = 0, kBatchEngineLanes = 1, kBatchEngineSlab = 2, kBatchEngines = 3 };
+inline int batch_engine_of(int kind) {
+  return kind == kBatchGemm ? kBatchEngineGemm : (kind == kBatchSlab ? kBatchEngineSlab : kBatchEngineLanes);
+}
 struct BatchLaunch {
   const BatchItem* items;
   const BatchPtrs* ptrs;
   const BatchTask* tasks;
   int64_t ntasks;
-  const int64_t* chunks;       // chunk c holds tasks [chunks[c], chunks[c+1])
-  int64_t nchunks;
-  unsigned long long* counter;
-  double* parts;               // partial sums of split items
-  unsigned* tile_cnt;          // segments finished per split tile or output group
+  const int64_t* chunks[kBatchEngines];  // engine e's chunk c holds tasks [chunks[e][c], chunks[e][c+1])
+  int64_t nchunks[kBatchEngines];
+  unsigned long long* counter;           // kBatchEngines chunk counters
+  double* parts;                         // partial sums of split items
+  unsigned* tile_cnt;                    // segments finished per split tile or output group
   int64_t n_cnt;
   int config;
   int slab_lds_doubles;
   int num_cus;
 };
-size_t batch_lds_bytes(int config, int slab_lds_doubles);
-// Workgroups of the batch kernel of a tile configuration one CU holds at once
-// (registers and the configuration's own LDS), or 0 on error.
-int batch_blocks_per_cu(int config);
+// Workgroups of the slab engine one CU holds at once with this much LDS per
+// workgroup (doubles), or 0 on error.
+int batch_slab_blocks_per_cu(int slab_lds_doubles);
 hipError_t launch_batch(const BatchLaunch& bl, hipStream_t s);
 
 // The picker's MLP (n_in -> hidden -> hidden -> n_out, ReLU, FP32).
