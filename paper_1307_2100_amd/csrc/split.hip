@@ -387,6 +387,263 @@ __global__ __launch_bounds__(64 * WGM * WGN) void split_gemm_bf16_kernel(SplitGe
   }
 }
 
+// BF16 digits, fed by direct global-to-LDS copies through two stages.  A
+// stage holds one k-step (32 contracted indices) of all S digits of the
+// tile's BM + BN rows, row after row (S x 64 bytes each, the digits' 16-byte
+// chunks swizzled within each digit), filled by global_load_lds_dwordx4
+// copies of 1 KB each.
+// Schedule of a k-step ks: the MFMAs go in phases t = 0 .. S-1 (digit t of B
+// against digits s < S - t of A).  The reads of B's remaining digits are
+// spread over phases 0 and 1; then each wavefront waits for its own copies
+// (vmcnt(0): those of k-step ks + 1, the only vector memory operations in
+// flight) and reads (lgkmcnt(0)), and the workgroup meets at a barrier.
+// After it, k-step ks + 1 is visible in the other stage and nothing reads
+// this one any more, so the copies of k-step ks + 2 into this stage and the
+// reads of k-step ks + 1's first fragments (A's digits, B's digit 0, into a
+// second register set) are spread over the remaining phases: a copy has one
+// whole k-step to land.  The last k-step is peeled off.
+template <int BM, int BN, int WGM, int WGN, int S>
+__global__ __launch_bounds__(64 * WGM * WGN) void split_gemm_bf16_dma_kernel(SplitGemmArgs p) {
+  constexpr int NW = WGM * WGN;
+  constexpr int KB = 32;                   // contracted indices per k-step (one MFMA depth)
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int AG = BM / 16, BG = BN / 16;
+  constexpr int NCOPY = (AG + BG) * S;     // 1 KB blocks per stage
+  constexpr int CPW = (NCOPY + NW - 1) / NW;
+  constexpr int STAGE = NCOPY * 1024;
+  constexpr int BP = S >= 3 ? 1 : 0;       // the barrier follows this phase
+  extern __shared__ __attribute__((aligned(16))) signed char dsm[];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  int64_t tm, tn;
+  xcd_tile(blockIdx.x, (p.Mp / BM) * (p.Np / BN), p.Mp / BM, p.Np / BN, &tm, &tn);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const u16* const PA = (const u16*)p.pa;
+  const u16* const PB = (const u16*)p.pb;
+  const int64_t rowlen = p.Kp * S;         // bf16 per row of the dense digit matrix
+  // Copy j of this wavefront fills 1 KB block c = wave + NW j of the stage
+  // (when c < NCOPY): its lane l lands 16 bytes at slot P = 64 c + l, and
+  // fetches the chunk stored there -- staged row r = P / (4 S), digit d, and
+  // contracted-index chunk q ^ ((r >> 2) & 3) for slot q of the digit's four.
+  // A copy thus reads whole runs of each row's S x 64 contiguous bytes.
+  const u16* base[CPW];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int c = wave + NW * j < NCOPY ? wave + NW * j : 0;
+    const int P = 64 * c + lane, r = P / (4 * S), w = P % (4 * S);
+    const int dig = w >> 2, q = (w & 3) ^ ((r >> 2) & 3);
+    base[j] = (r < BM ? PA + (m0 + r) * rowlen : PB + (n0 + r - BM) * rowlen) + dig * KB + q * 8;
+  }
+  auto copy1 = [&](int j, int64_t ks, int stage) {
+    const int c = wave + NW * j;
+    if (c < NCOPY)
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(base[j] + ks * (S * KB)),
+                                       (void __attribute__((address_space(3)))*)(dsm + stage * STAGE + c * 1024), 16,
+                                       0, 0);
+  };
+  // A fragment: rows 16 g .. 16 g + 15, lane l reading row l%16's chunk l/16
+  // of one digit; for odd S the swizzle puts the 16 rows' chunks in 16
+  // distinct 16-byte bank groups of the LDS's 64 banks (S = 2 and 4 leave 2-
+  // and 4-way conflicts).
+  const int lanepart = (lane & 15) * (S * 64) + (((lane >> 4) ^ ((lane >> 2) & 3)) << 4);
+  auto afrag = [&](int stage, int dig, int i) {
+    return *(const bf8*)(dsm + stage * STAGE + (wm * TM + i) * (16 * S * 64) + dig * 64 + lanepart);
+  };
+  auto bfrag = [&](int stage, int dig, int j) {
+    return *(const bf8*)(dsm + stage * STAGE + (AG + wn * TN + j) * (16 * S * 64) + dig * 64 + lanepart);
+  };
+
+  // Level g (digit pair s + t = g) sums: levels 0, 1, 2 exact in their own
+  // FP32 accumulators for the intervals below, deeper levels together.
+  constexpr int NACC = S < 4 ? S : 4;
+  f4 acc[NACC][TM][TN];
+  double acc64[TM][TN][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+#pragma unroll
+      for (int g = 0; g < NACC; ++g) acc[g][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+    }
+  // FP32 level sums to FP64 before they could round: level g adds g + 1
+  // digit products below 2^16 per contracted index, so it stays exact for
+  // 256 / (g + 1) indices: level 0 every 8 k-steps, level 1 every 4, level 2
+  // and the shared deeper levels every 2.
+  auto flush = [&](int64_t ks, bool last_step) {
+#pragma unroll
+    for (int g = 0; g < NACC; ++g) {
+      const int every = g == 0 ? 8 : (g == 1 ? 4 : 2);
+      if (((ks + 1) % every) != 0 && !last_step) continue;
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[g][i][j][r];
+          acc[g][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  };
+  // MFMAs of phase t (A digits s < S - t against B digit t)
+  auto phase_mfma = [&](int t, const bf8 (&af)[S][TM], const bf8 (&bt)[TN], int q0, int q1) {
+    // products numbered q = (s, i, j) in this phase; only those in [q0, q1)
+    int q = 0;
+#pragma unroll
+    for (int s_ = 0; s_ + t < S; ++s_) {
+      const int g = s_ + t < NACC ? s_ + t : NACC - 1;
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j, ++q)
+          if (q >= q0 && q < q1)
+            acc[g][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s_][i], bt[j], acc[g][i][j], 0, 0, 0);
+    }
+  };
+  // number of MFMAs of phase t
+  auto nmfma = [](int t) { return (S - t) * TM * TN; };
+
+  bf8 a0[S][TM], a1[S][TM];
+  bf8 b[S][TN];
+  const int64_t ksteps = p.Kp / KB, last = ksteps - 1;
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) copy1(j, 0, 0);
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) copy1(j, last > 0 ? 1 : 0, 1);
+  __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int d = 0; d < S; ++d)
+#pragma unroll
+    for (int i = 0; i < TM; ++i) a0[d][i] = afrag(0, d, i);
+#pragma unroll
+  for (int j = 0; j < TN; ++j) b[0][j] = bfrag(0, 0, j);
+
+  // one k-step with a next one: reads of stage cur, then copies into stage
+  // cur (of k-step ks + 2, or of the last one again: a stage nobody reads
+  // after the barrier) and reads of stage cur ^ 1; (af) holds this k-step's A
+  // digits, (an) receives the next
+  auto kstep = [&](int64_t ks, const bf8 (&af)[S][TM], bf8 (&an)[S][TM]) {
+    const int cur = (int)(ks & 1), nxt = cur ^ 1;
+    const int64_t kc = ks + 2 <= last ? ks + 2 : last;
+    // phases 0 .. BP: reads of B digits 1 .. S-1
+    constexpr int NB = (S - 1) * TN;          // B fragments still to read
+#pragma unroll
+    for (int t = 0; t <= BP; ++t) {
+      const int n = nmfma(t);
+#pragma unroll
+      for (int q = 0; q < n; ++q) {
+        __builtin_amdgcn_sched_barrier(0);
+        phase_mfma(t, af, b[t], q, q + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        // B reads: those numbered [before NB / span, (before + 1) NB / span)
+        // after the MFMA numbered (before) of phases 0 .. BP
+        const int before = (t == 0 ? 0 : nmfma(0)) + q;
+        const int span = BP == 0 ? nmfma(0) : nmfma(0) + nmfma(1);
+#pragma unroll
+        for (int x = before * NB / span; x < (before + 1) * NB / span; ++x)
+          b[1 + x / TN][x % TN] = bfrag(cur, 1 + x / TN, x % TN);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // this wavefront's copies of the next k-step, and its reads of this one
+    // (so no read of a stage is in flight when the copies into it start)
+    __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (0 << 8));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    // phases BP+1 .. S-1: copies into this stage and reads of the next
+    // k-step's fragments spread over them
+    constexpr int NR = S * TM + TN;
+    int span = 0;
+#pragma unroll
+    for (int t = BP + 1; t < S; ++t) span += nmfma(t);
+    int before = 0;
+#pragma unroll
+    for (int t = BP + 1; t < S; ++t) {
+      const int n = nmfma(t);
+#pragma unroll
+      for (int q = 0; q < n; ++q, ++before) {
+        __builtin_amdgcn_sched_barrier(0);
+        phase_mfma(t, af, b[t], q, q + 1);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = before * CPW / span; j < (before + 1) * CPW / span; ++j) copy1(j, kc, cur);
+#pragma unroll
+        for (int x = before * NR / span; x < (before + 1) * NR / span; ++x) {
+          if (x < S * TM)
+            an[x / TM][x % TM] = afrag(nxt, x / TM, x % TM);
+          else
+            b[0][x - S * TM] = bfrag(nxt, 0, x - S * TM);
+        }
+      }
+    }
+    if (span == 0) {  // no phase after the barrier (S = 1): copy and read here
+#pragma unroll
+      for (int j = 0; j < CPW; ++j) copy1(j, kc, cur);
+#pragma unroll
+      for (int d = 0; d < S; ++d)
+#pragma unroll
+        for (int i = 0; i < TM; ++i) an[d][i] = afrag(nxt, d, i);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[0][j] = bfrag(nxt, 0, j);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    flush(ks, false);
+  };
+  int64_t ks = 0;
+  for (; ks + 1 < last; ks += 2) {
+    kstep(ks, a0, a1);
+    kstep(ks + 1, a1, a0);
+  }
+  if (ks < last) {
+    kstep(ks, a0, a1);
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a0[d][i] = a1[d][i];
+    ++ks;
+  }
+  // the last k-step: read B's remaining digits, then every phase
+  {
+    const int cur = (int)(ks & 1);
+#pragma unroll
+    for (int t = 1; t < S; ++t)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[t][j] = bfrag(cur, t, j);
+#pragma unroll
+    for (int t = 0; t < S; ++t) phase_mfma(t, a0, b[t], 0, nmfma(t));
+    flush(ks, true);
+  }
+  // the copies issued during the k-step before (of the last k-step again)
+  // land before the workgroup's LDS can be handed to another
+  __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = m0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
+      if (m >= p.M) continue;
+      const double sm_ = p.sa[m] * p.unit * p.alpha;
+      const int64_t cm = off_at(p.cM, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t n = n0 + wn * WN + j * 16 + (lane & 15);
+        if (n >= p.N) continue;
+        double* dst = p.C + cm + off_at(p.cN, n);
+        double v = sm_ * p.sb[n] * acc64[i][j][r];
+        if (p.beta != 0.0) v += p.beta * *dst;
+        *dst = v;
+      }
+    }
+  }
+}
+
 // FP8 E4M3 digits: v_mfma_scale_f32_16x16x128_f8f6f4 with the per-plane powers
 // of two as E8M0 block scales.  Lane l holds A[l%16][32(l/16) .. +31]; the
 // accumulator element r holds D[4(l/16) + r][l%16].
@@ -1242,7 +1499,11 @@ hipError_t launch_split_gemm(const SplitGemmArgs& a, bool fp8, hipStream_t s) {
     else
       return hipErrorInvalidValue;
   } else if constexpr (S <= 5) {
-    hipLaunchKernelGGL((split_gemm_bf16_kernel<128, 64, 4, 2, S>), grid, dim3(512), 0, s, a);
+    constexpr int bytes = 2 * (128 / 16 + 64 / 16) * S * 1024;
+    static std::atomic<uint64_t> allowed{0};
+    const hipError_t e = allow_dynamic_lds((const void*)split_gemm_bf16_dma_kernel<128, 64, 4, 2, S>, bytes, allowed);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((split_gemm_bf16_dma_kernel<128, 64, 4, 2, S>), grid, dim3(512), bytes, s, a);
   } else if constexpr (S <= kSplitMaxBf16) {
     hipLaunchKernelGGL((split_gemm_bf16_kernel<64, 64, 2, 2, S>), grid, dim3(256), 0, s, a);
   } else {
