@@ -89,8 +89,68 @@ tc_status analyze_args(int ra, const int64_t* ea, const int64_t* sa, const int32
 struct OffsTargets {
   tc::Offs *aM, *aK, *aL, *bN, *bK, *bL, *cM, *cN, *cL;
 };
+// Block tables of a contracted group of several modes, for inner products
+// with lanes along the contracted range: the entries go in blocks of at most
+// 64 over two modes p and q -- A's and B's stride-1 modes when they differ
+// (then b_p x b_q = 8 x 8 where the extents allow, so both operands are read
+// in runs of neighbours instead of one of them with strided lanes), else the
+// stride-1 mode (up to 64 of it) and the next mode.  Blocks go column-major
+// over (p's block, q's block, the other modes); each gets its base offset in
+// A and B and its extents along p and q (ragged at the ends of p and q).
+void build_k_blocks(const tc::Group& g, tc::BatchItem& it, std::vector<int64_t>& host,
+                    std::vector<std::pair<tc::Offs*, size_t>>& pos) {
+  int p = -1, q = -1;
+  for (int d = 0; d < g.n; ++d) {
+    if (g.str[tc::SA][d] == 1 && p < 0) p = d;
+    if (g.str[tc::SB][d] == 1 && q < 0) q = d;
+  }
+  const bool f1 = p >= 0 && q >= 0 && p != q;
+  if (!f1) {
+    if (p < 0) p = q >= 0 ? q : 0;
+    q = p == 0 ? 1 : 0;  // g.n >= 2
+  }
+  const int64_t ep = g.ext[p], eq = g.ext[q];
+  const int64_t bp = f1 ? std::min<int64_t>(ep, 8) : std::min<int64_t>(ep, 64);
+  const int64_t bq = std::min<int64_t>(eq, 64 / bp);
+  int64_t ext[TC_MAX_RANK], sa[TC_MAX_RANK], sb[TC_MAX_RANK];
+  int n = 0;
+  ext[n] = (ep + bp - 1) / bp, sa[n] = bp * g.str[tc::SA][p], sb[n] = bp * g.str[tc::SB][p], ++n;
+  ext[n] = (eq + bq - 1) / bq, sa[n] = bq * g.str[tc::SA][q], sb[n] = bq * g.str[tc::SB][q], ++n;
+  for (int d = 0; d < g.n; ++d)
+    if (d != p && d != q) ext[n] = g.ext[d], sa[n] = g.str[tc::SA][d], sb[n] = g.str[tc::SB][d], ++n;
+  int64_t nblk = 1;
+  for (int d = 0; d < n; ++d) nblk *= ext[d];
+  it.kblk = 1;
+  it.kbp = (int)bp;
+  it.nblk = nblk;
+  it.ksa_p = g.str[tc::SA][p], it.ksa_q = g.str[tc::SA][q];
+  it.ksb_p = g.str[tc::SB][p], it.ksb_q = g.str[tc::SB][q];
+  tc::Offs* dst[3] = {&it.g.aK, &it.g.bK, &it.klim};
+  for (int t = 0; t < 3; ++t) {
+    *dst[t] = tc::Offs{};
+    pos.push_back({dst[t], host.size()});
+    int64_t idx[TC_MAX_RANK] = {};
+    int64_t off = 0;
+    const int64_t* st = t == 0 ? sa : sb;
+    for (int64_t j = 0; j < nblk; ++j) {
+      if (t < 2) {
+        host.push_back(off);
+      } else {
+        const int64_t lp = std::min(bp, ep - idx[0] * bp), lq = std::min(bq, eq - idx[1] * bq);
+        host.push_back(lp | (lq << 8));
+      }
+      for (int d = 0; d < n; ++d) {
+        if (t < 2) off += st[d];
+        if (++idx[d] < ext[d]) break;
+        if (t < 2) off -= st[d] * ext[d];
+        idx[d] = 0;
+      }
+    }
+  }
+}
+
 void build_tables(const tc::Analysis& an, const OffsTargets& t, std::vector<int64_t>& host,
-                  std::vector<std::pair<tc::Offs*, size_t>>& pos) {
+                  std::vector<std::pair<tc::Offs*, size_t>>& pos, bool skip_k = false) {
   const tc::Group* G = an.g;
   struct Want {
     int group, slot;
@@ -106,6 +166,7 @@ void build_tables(const tc::Analysis& an, const OffsTargets& t, std::vector<int6
       want[w].dst->stride = g.n == 1 ? g.str[want[w].slot][0] : 0;
       continue;
     }
+    if (skip_k && want[w].group == tc::GK) continue;  // the caller builds block tables
     const int64_t n = g.size();
     pos.push_back({want[w].dst, host.size()});
     // column-major walk of the group's multi-index with a running offset (no
@@ -448,12 +509,14 @@ struct tc_batch_s {
         // memory-bound: groups of outputs; long contracted ranges in segments
         const bool lk = it.kind == tc::kBatchLanesK;
         const int64_t outputs = it.g.M * it.g.N * it.g.L;
-        const int64_t target = lk ? 16384 : 512;  // contracted indices per segment
+        // contracted indices per segment (blocked items: blocks of up to 64)
+        const int64_t target = lk ? (it.kblk ? 256 : 16384) : 512;
+        const int64_t range = it.kblk ? it.nblk : it.g.K;
         int S = 1;
-        int64_t len = it.g.K;
-        if (it.g.K > 2 * target) {
-          S = (int)((it.g.K + target - 1) / target);
-          len = (it.g.K + S - 1) / S;
+        int64_t len = range;
+        if (range > 2 * target) {
+          S = (int)((range + target - 1) / target);
+          len = (range + S - 1) / S;
         }
         it.ksplit = S;
         it.seg_len = len;
@@ -467,7 +530,7 @@ struct tc_batch_s {
             n_cnt += outputs;
           }
           const int64_t ntask = (outputs * S + tc::kLanesKOutputs - 1) / tc::kLanesKOutputs;
-          const double cost = 16.0 * tc::kLanesKOutputs * (double)len / 8e12;
+          const double cost = 16.0 * tc::kLanesKOutputs * (double)len * (it.kblk ? 64.0 : 1.0) / 8e12;
           for (int64_t t = 0; t < ntask; ++t) tasks.push_back({cost, tc::BatchTask{i, 0, t}});
         } else {
           // 256 outputs along lanes per task, one task per (output group, segment)
@@ -1068,9 +1131,13 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
                      host, pos);
         s = fill_slab(an, it.b, tc::kBatchSlabLdsDoubles, host, pos);
       } else {
+        // inner products over a contracted group of several modes address
+        // it through block tables
+        const bool kblk = an.kernel == tc::Analysis::KERNEL_LANES_K && an.g[tc::GK].n >= 2 && !an.empty_out;
         build_tables(an, OffsTargets{&it.g.aM, &it.g.aK, &it.g.aL, &it.g.bN, &it.g.bK, &it.g.bL, &it.g.cM, &it.g.cN,
                                      &it.g.cL},
-                     host, pos);
+                     host, pos, kblk);
+        if (kblk) build_k_blocks(an.g[tc::GK], it, host, pos);
       }
     } catch (const std::bad_alloc&) {
       s = fail(TC_ERR_NOMEM, "host allocation of offset tables failed");

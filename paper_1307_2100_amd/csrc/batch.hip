@@ -76,9 +76,17 @@ TC_DEV void batch_lanes_k(const BatchItem& it, const GettParams& p, const BatchT
   const int64_t l = r / p.N;
   const double* __restrict__ A = p.A + off_at(p.aL, l) + off_at(p.aM, m);
   const double* __restrict__ B = p.B + off_at(p.bL, l) + off_at(p.bN, n);
+  const int64_t kend = it.kblk ? it.nblk : p.K;
   const int64_t k0 = (int64_t)s * it.seg_len;
-  const int64_t k1 = k0 + it.seg_len < p.K ? k0 + it.seg_len : p.K;
-  const double v = batch_wave_sum(lanes_k_dot_flat<8>(A, B, p.aK, p.bK, k0, k1, lane));
+  const int64_t k1 = k0 + it.seg_len < kend ? k0 + it.seg_len : kend;
+  double v;
+  if (it.kblk) {
+    const int lp = lane % it.kbp, lq = lane / it.kbp;
+    v = batch_wave_sum(lanes_k_blocks<8>(A, B, p.aK.tab, p.bK.tab, it.klim.tab, k0, k1, lp * it.ksa_p + lq * it.ksa_q,
+                                         lp * it.ksb_p + lq * it.ksb_q, lp, lq));
+  } else {
+    v = batch_wave_sum(lanes_k_dot_flat<8>(A, B, p.aK, p.bK, k0, k1, lane));
+  }
   if (S == 1) {
     if (lane == 0) batch_store(p, m, n, l, v);
     return;

@@ -376,9 +376,18 @@ struct BatchItem {       // one contraction of a batch (layout only)
   int64_t tilesM, tilesN;
   int ksplit;            // contracted segments per task group (1 = none)
   int n_fastest;         // kind 3: consecutive lanes along n (else along m)
-  int64_t seg_len;       // contracted indices per segment
+  int64_t seg_len;       // contracted indices per segment (kind 2 with kblk: blocks)
   int64_t part_off;      // first partial sum of this item (in doubles)
   int64_t cnt_off;       // first completion counter of this item
+  // Kind 2 over a contracted group of several modes: its entries in blocks
+  // of at most 64, lane l taking entry (l % kbp) of mode p and (l / kbp) of
+  // mode q of a block.  g.aK / g.bK hold each block's base offset in A and
+  // B, klim its extents along p and q (bits 0-7 and 8-15).
+  int kblk;              // 1: blocked addressing
+  int kbp;               // block extent along mode p
+  int64_t nblk;          // blocks
+  int64_t ksa_p, ksa_q, ksb_p, ksb_q;  // strides of modes p and q in A and B
+  Offs klim;
 };
 struct BatchPtrs {       // per execution
   const double* A;

@@ -168,6 +168,54 @@ TC_DEV double lanes_k_dot_flat(const double* __restrict__ A, const double* __res
                 : lanes_k_steps<U, false, false>(A, B, aK, bK, k0, k1, lane);
 }
 
+// Lanes along k over a contracted group walked in blocks of at most 64
+// entries: this lane's share of the sum over blocks [j0, j1), block j adding
+// A[ta[j] + la] B[tb[j] + lb] where the lane's position (lp, lq) lies inside
+// the block's extents (tl[j]: bits 0-7 along p, 8-15 along q).  The block
+// tables are indexed by wavefront-uniform j (scalar loads, one per 64 entries
+// instead of one per entry), and the next step's entries are looked up while
+// the current step's loads are in flight.
+template <int U>
+TC_DEV double lanes_k_blocks(const double* __restrict__ A, const double* __restrict__ B,
+                             const int64_t* __restrict__ ta, const int64_t* __restrict__ tb,
+                             const int64_t* __restrict__ tl, int64_t j0, int64_t j1, int64_t la, int64_t lb, int lp,
+                             int lq) {
+  double accu[U];
+  int64_t oa[U], ob[U];
+  bool ok[U];
+  auto look = [&](int u, int64_t j) {
+    const int64_t jj = j < j1 ? j : j0;
+    const int64_t lim = tl[jj];
+    ok[u] = j < j1 && lp < (int)(lim & 255) && lq < (int)((lim >> 8) & 255);
+    oa[u] = ta[jj] + (ok[u] ? la : 0);
+    ob[u] = tb[jj] + (ok[u] ? lb : 0);
+  };
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    accu[u] = 0.0;
+    look(u, j0 + u);
+  }
+  for (int64_t j = j0; j < j1; j += U) {
+    double a[U], b[U];
+    bool v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a[u] = A[oa[u]];
+      b[u] = B[ob[u]];
+      v[u] = ok[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) look(u, j + U + u);
+#pragma unroll
+    for (int u = 0; u < U; ++u) accu[u] += v[u] ? a[u] * b[u] : 0.0;
+  }
+#pragma unroll
+  for (int w = U / 2; w >= 1; w /= 2)
+#pragma unroll
+    for (int u = 0; u < w; ++u) accu[u] += accu[u + w];
+  return accu[0];
+}
+
 template <bool TA, bool TB>
 TC_DEV double lanes_out_steps(const double* __restrict__ A, const double* __restrict__ B, const Offs& aK,
                               const Offs& bK, int64_t k0, int64_t k1) {
