@@ -427,21 +427,34 @@ __global__ __launch_bounds__(64 * WGM * WGN) void split_gemm_bf16_dma_kernel(Spl
   // (when c < NCOPY): its lane l lands 16 bytes at slot P = 64 c + l, and
   // fetches the chunk stored there -- staged row r = P / (4 S), digit d, and
   // contracted-index chunk q ^ ((r >> 2) & 3) for slot q of the digit's four.
-  // A copy thus reads whole runs of each row's S x 64 contiguous bytes.
-  const u16* base[CPW];
+  // A copy thus reads whole runs of each row's S x 64 contiguous bytes.  The
+  // first AG S blocks are A's rows, a whole number per wavefront, so copy j
+  // reads A for j < AG S / NW and B after.  Its address is a uniform base (the
+  // tile's first row of that operand, advanced per k-step) plus a 32-bit
+  // per-lane byte offset (the launch keeps BM rows of digits below 2^31
+  // bytes), and its LDS address is uniform: no vector arithmetic per copy.
+  static_assert((AG * S) % NW == 0, "A's blocks must split evenly over the wavefronts");
+  constexpr int CPA = AG * S / NW;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  uint32_t voff[CPW];
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
     const int c = wave + NW * j < NCOPY ? wave + NW * j : 0;
     const int P = 64 * c + lane, r = P / (4 * S), w = P % (4 * S);
     const int dig = w >> 2, q = (w & 3) ^ ((r >> 2) & 3);
-    base[j] = (r < BM ? PA + (m0 + r) * rowlen : PB + (n0 + r - BM) * rowlen) + dig * KB + q * 8;
+    const int rr = j < CPA ? r : r - BM;
+    voff[j] = (uint32_t)(((int64_t)rr * rowlen + dig * KB + q * 8) * 2);
   }
+  const char* const tileA = (const char*)(PA + m0 * rowlen);
+  const char* const tileB = (const char*)(PB + n0 * rowlen);
   auto copy1 = [&](int j, int64_t ks, int stage) {
-    const int c = wave + NW * j;
-    if (c < NCOPY)
-      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(base[j] + ks * (S * KB)),
+    const int c = wave_u + NW * j;
+    if (c < NCOPY) {
+      const char* g = (j < CPA ? tileA : tileB) + ks * (S * KB * 2);
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(g + voff[j]),
                                        (void __attribute__((address_space(3)))*)(dsm + stage * STAGE + c * 1024), 16,
                                        0, 0);
+    }
   };
   // A fragment: rows 16 g .. 16 g + 15, lane l reading row l%16's chunk l/16
   // of one digit; for odd S the swizzle puts the 16 rows' chunks in 16
@@ -1499,6 +1512,11 @@ hipError_t launch_split_gemm(const SplitGemmArgs& a, bool fp8, hipStream_t s) {
     else
       return hipErrorInvalidValue;
   } else if constexpr (S <= 5) {
+    // the copy-fed kernel addresses a tile's rows by 32-bit byte offsets
+    if ((double)a.Kp * S * 2.0 * 128.0 >= 2147483648.0) {
+      hipLaunchKernelGGL((split_gemm_bf16_kernel<128, 64, 4, 2, S>), grid, dim3(512), 0, s, a);
+      return hipGetLastError();
+    }
     constexpr int bytes = 2 * (128 / 16 + 64 / 16) * S * 1024;
     static std::atomic<uint64_t> allowed{0};
     const hipError_t e = allow_dynamic_lds((const void*)split_gemm_bf16_dma_kernel<128, 64, 4, 2, S>, bytes, allowed);

@@ -242,3 +242,19 @@ def test_split_long_contraction_flushes_level_sums(precision):
         err = componentwise_error(got, ref, absr)
         print(precision, kind, "K=9000 componentwise error %.3e" % err)
         assert err <= t
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("K", [1_600_000, 1_700_000])
+def test_split_bf16_very_long_contracted_range(K):
+    """Five BF16 digits over 1.6 and 1.7 million contracted indices: the
+    copy-fed digit GEMM addresses a tile's 128 rows of digits by 32-bit byte
+    offsets, up to 2.03e9 bytes at K = 1.6e6; at K = 1.7e6 the rows would
+    pass 2^31 bytes and the launch takes the register-staged kernel instead.
+    Exact on integers."""
+    labA, labB, labC = "ik", "kj", "ij"
+    ext = {"i": 3, "k": K, "j": 2}
+    A, B = synth.make_operands(35, labA, labB, ext, kind="integers")
+    got, info = _run(labA, labB, labC, A, B, "split_bf16")
+    assert info["split_slices"] == 5
+    assert np.array_equal(got, oracle.contract(A, labA, B, labB, labC))
