@@ -1172,18 +1172,24 @@ __global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_pipe_kernel(CrtGemmAr
   const signed char* const PA = g.pa + (int64_t)mod * g.Mp * g.Kp + m0 * BK;
   const signed char* const PB = g.pb + (int64_t)mod * g.Np * g.Kp + n0 * BK;
   const int64_t kstepA = g.Mp * BK, kstepB = g.Np * BK;
-  // this lane's source address of each of its copies at k-step 0 (rows 16c .. 16c+15, chunk lane/16)
-  const signed char* base[CPW];
+  // Copy j of this wavefront fills 1 KB block c = wave + NW j (rows 16c ..
+  // 16c+15, chunk lane/16); the first BM / 16 blocks are A's, a whole number
+  // per wavefront, so copy j reads A for j < BM / (16 NW).  Its address is a
+  // uniform base (the operand's k-step) plus this lane's 32-bit offset, and
+  // its LDS address is uniform: no vector arithmetic per copy.
+  static_assert((BM / 16) % NW == 0, "A's copies must split evenly over the wavefronts");
+  constexpr int CPA = BM / 16 / NW;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  uint32_t voff[CPW];
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
-    const int c = wave + NW * j;
-    const int r = 16 * c + (lane & 15);
-    base[j] = (16 * c < BM ? PA + r * BK : PB + (r - BM) * BK) + (lane >> 4) * 16;
+    const int r = 16 * (wave + NW * j) + (lane & 15);
+    voff[j] = (uint32_t)((j < CPA ? r : r - BM) * BK + (lane >> 4) * 16);
   }
   auto copy1 = [&](int j, int64_t ks, int stage) {
-    const int c = wave + NW * j;
-    const int64_t off = 16 * c < BM ? ks * kstepA : ks * kstepB;
-    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(base[j] + off),
+    const int c = wave_u + NW * j;
+    const signed char* base = j < CPA ? PA + ks * kstepA : PB + ks * kstepB;
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(base + voff[j]),
                                      (void __attribute__((address_space(3)))*)(dsm + stage * STAGE + c * 1024), 16,
                                      0, 0);
   };
