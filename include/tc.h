@@ -265,6 +265,8 @@ tc_status tc_batch_execute(tc_batch_t batch, const double* const* A, const doubl
  * x depth: 64x64x16, 32x32x16, 32x32x64, 64x64x32, 32x32x128, 64x64x64);
  * use_graph: 0 launches eagerly, 1 replays a hipGraph. */
 tc_status tc_batch_set_options(tc_batch_t batch, int tile_config, int use_graph);
+/* ntasks: the tasks of the persistent engines plus the workgroups of the slab
+ * contractions large enough to run as launches of their own. */
 tc_status tc_batch_query(tc_batch_t batch, int64_t* ntasks, int* tile_config, int* use_graph);
 /* Autotuner: times every tile configuration on the given buffers (C is
  * overwritten; eager launches, median of three) and keeps the fastest, which

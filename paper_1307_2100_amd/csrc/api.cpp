@@ -420,6 +420,8 @@ struct tc_batch_s {
   int64_t nchunks = 0;                          // chunks of all engines
   int64_t chunk_base[tc::kBatchEngines] = {};   // engine e's bounds start at d_chunks + chunk_base[e]
   int64_t engine_chunks[tc::kBatchEngines] = {};
+  std::vector<int> direct_items;                // slab items launched on their own
+  std::vector<int64_t> direct_blocks;
   tc::BatchPtrs* h_ptrs = nullptr;
   hipStream_t capture_stream = nullptr;
   hipEvent_t done = nullptr;
@@ -494,6 +496,8 @@ struct tc_batch_s {
     std::vector<HT> tasks;
     n_cnt = 0;
     n_parts = 0;
+    direct_items.clear();
+    direct_blocks.clear();
     // Slab tasks run in their own launch with 16 KB of LDS per workgroup (the
     // budget measured best for the grid contractions on their own).
     slab_lds = tc::kBatchSlabLdsDoubles;
@@ -566,6 +570,12 @@ struct tc_batch_s {
           for (int sg = 0; sg < S; ++sg) tasks.push_back({cost, tc::BatchTask{i, sg, t}});
       } else {
         const int64_t nt = (it.b.L + it.b.P - 1) / it.b.P;
+        if (nt >= (int64_t)tc::kBatchDirectSlabBlocksPerCu * num_cus && nt <= 0x7fffffffLL) {
+          // fills the chip on its own: a launch of its own, no task-list overhead
+          direct_items.push_back(i);
+          direct_blocks.push_back(nt);
+          continue;
+        }
         const double bytes = 8.0 * it.b.P * (it.b.a.size + it.b.b.size + it.b.c.size);
         const double cost = bytes / 8e12;
         for (int64_t t = 0; t < nt; ++t) tasks.push_back({cost, tc::BatchTask{i, 0, t}});
@@ -650,6 +660,9 @@ struct tc_batch_s {
     bl.config = config;
     bl.slab_lds_doubles = slab_lds;
     bl.num_cus = num_cus;
+    bl.direct_items = direct_items.data();
+    bl.direct_blocks = direct_blocks.data();
+    bl.ndirect = (int)direct_items.size();
     return tc::launch_batch(bl, st);
   }
 
@@ -1219,7 +1232,10 @@ tc_status tc_batch_set_options(tc_batch_t batch, int tile_config, int use_graph)
 
 tc_status tc_batch_query(tc_batch_t batch, int64_t* ntasks, int* tile_config, int* use_graph) {
   if (!batch) return fail(TC_ERR_INVALID_ARG, "batch is null");
-  if (ntasks) *ntasks = batch->ntasks;
+  if (ntasks) {
+    *ntasks = batch->ntasks;
+    for (int64_t b : batch->direct_blocks) *ntasks += b;
+  }
   if (tile_config) *tile_config = batch->config;
   if (use_graph) *use_graph = batch->use_graph;
   return TC_OK;

@@ -228,6 +228,17 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict_
   }
 }
 
+// One large slab item on its own: workgroup b takes its batch indices
+// b P .. b P + P - 1, with the pointers of this execution.
+__global__ __launch_bounds__(256) void batch_slab_direct_kernel(const BatchItem* __restrict__ items,
+                                                                const BatchPtrs* __restrict__ ptrs, int item) {
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  const BatchItem& it = items[item];
+  const BatchPtrs pt = ptrs[item];
+  batched_slab(it.b, it.swapped ? pt.B : pt.A, it.swapped ? pt.A : pt.B, pt.C, pt.alpha, pt.beta,
+               (int64_t)blockIdx.x * it.b.P, smem);
+}
+
 __global__ void batch_reset_kernel(unsigned long long* counter, unsigned* tile_cnt, int64_t n_cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < kBatchEngines) counter[i] = 0ull;
@@ -267,7 +278,13 @@ hipError_t launch_cfg(const BatchLaunch& bl, hipStream_t s) {
   // inner products and matrix-vector groups, then the slabs
   if ((e = launch_engine<BM, BN, BK, kBatchEngineGemm>(bl, s)) != hipSuccess) return e;
   if ((e = launch_engine<BM, BN, BK, kBatchEngineLanes>(bl, s)) != hipSuccess) return e;
-  return launch_engine<BM, BN, BK, kBatchEngineSlab>(bl, s);
+  if ((e = launch_engine<BM, BN, BK, kBatchEngineSlab>(bl, s)) != hipSuccess) return e;
+  for (int d = 0; d < bl.ndirect; ++d) {
+    hipLaunchKernelGGL(batch_slab_direct_kernel, dim3((unsigned)bl.direct_blocks[d]), dim3(256),
+                       (size_t)bl.slab_lds_doubles * sizeof(double), s, bl.items, bl.ptrs, bl.direct_items[d]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -281,7 +298,7 @@ int batch_slab_blocks_per_cu(int slab_lds_doubles) {
 }
 
 hipError_t launch_batch(const BatchLaunch& bl, hipStream_t s) {
-  if (bl.ntasks == 0) return hipSuccess;
+  if (bl.ntasks == 0 && bl.ndirect == 0) return hipSuccess;
   switch (bl.config) {
 #define TC_BCFG(id, bm, bn, bk) \
   case id: return launch_cfg<bm, bn, bk>(bl, s);

@@ -420,7 +420,15 @@ struct BatchLaunch {
   int config;
   int slab_lds_doubles;
   int num_cus;
+  // slab items large enough to fill the chip on their own: one launch each,
+  // a workgroup per P batch indices (host arrays: item index, workgroups)
+  const int* direct_items;
+  const int64_t* direct_blocks;
+  int ndirect;
 };
+// Slab items with at least this many workgroups per CU run as launches of
+// their own instead of tasks of the persistent slab engine.
+constexpr int kBatchDirectSlabBlocksPerCu = 16;
 // Workgroups of the slab engine one CU holds at once with this much LDS per
 // workgroup (doubles), or 0 on error.
 int batch_slab_blocks_per_cu(int slab_lds_doubles);
