@@ -514,7 +514,7 @@ struct tc_batch_s {
         const bool lk = it.kind == tc::kBatchLanesK;
         const int64_t outputs = it.g.M * it.g.N * it.g.L;
         // contracted indices per segment (blocked items: blocks of up to 64)
-        const int64_t target = lk ? (it.kblk ? 256 : 16384) : 512;
+        const int64_t target = lk ? (it.kblk ? 2048 : 16384) : 512;
         const int64_t range = it.kblk ? it.nblk : it.g.K;
         int S = 1;
         int64_t len = range;
