@@ -664,6 +664,7 @@ struct tc_batch_s {
     bl.direct_items = direct_items.data();
     bl.direct_blocks = direct_blocks.data();
     bl.ndirect = (int)direct_items.size();
+    bl.host_items = items.data();
     return tc::launch_batch(bl, st);
   }
 

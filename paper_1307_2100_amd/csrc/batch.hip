@@ -229,14 +229,14 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict_
 }
 
 // One large slab item on its own: workgroup b takes its batch indices
-// b P .. b P + P - 1, with the pointers of this execution.
-__global__ __launch_bounds__(256) void batch_slab_direct_kernel(const BatchItem* __restrict__ items,
-                                                                const BatchPtrs* __restrict__ ptrs, int item) {
+// b P .. b P + P - 1.  The layout comes by value; the pointers and scalars
+// of this execution from the staged pointer array.
+__global__ __launch_bounds__(256) void batch_slab_direct_kernel(BatchedParams bp, const BatchPtrs* __restrict__ ptrs,
+                                                                int item, int swapped) {
   extern __shared__ __attribute__((aligned(16))) double smem[];
-  const BatchItem& it = items[item];
   const BatchPtrs pt = ptrs[item];
-  batched_slab(it.b, it.swapped ? pt.B : pt.A, it.swapped ? pt.A : pt.B, pt.C, pt.alpha, pt.beta,
-               (int64_t)blockIdx.x * it.b.P, smem);
+  batched_slab(bp, swapped ? pt.B : pt.A, swapped ? pt.A : pt.B, pt.C, pt.alpha, pt.beta, (int64_t)blockIdx.x * bp.P,
+               smem);
 }
 
 __global__ void batch_reset_kernel(unsigned long long* counter, unsigned* tile_cnt, int64_t n_cnt) {
@@ -280,8 +280,9 @@ hipError_t launch_cfg(const BatchLaunch& bl, hipStream_t s) {
   if ((e = launch_engine<BM, BN, BK, kBatchEngineLanes>(bl, s)) != hipSuccess) return e;
   if ((e = launch_engine<BM, BN, BK, kBatchEngineSlab>(bl, s)) != hipSuccess) return e;
   for (int d = 0; d < bl.ndirect; ++d) {
+    const BatchItem& it = bl.host_items[bl.direct_items[d]];
     hipLaunchKernelGGL(batch_slab_direct_kernel, dim3((unsigned)bl.direct_blocks[d]), dim3(256),
-                       (size_t)bl.slab_lds_doubles * sizeof(double), s, bl.items, bl.ptrs, bl.direct_items[d]);
+                       (size_t)bl.slab_lds_doubles * sizeof(double), s, it.b, bl.ptrs, bl.direct_items[d], it.swapped);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;

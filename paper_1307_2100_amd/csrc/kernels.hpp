@@ -425,6 +425,7 @@ struct BatchLaunch {
   const int* direct_items;
   const int64_t* direct_blocks;
   int ndirect;
+  const BatchItem* host_items;  // host copy of the items (layouts of the direct launches)
 };
 // Slab items with at least this many workgroups per CU run as launches of
 // their own instead of tasks of the persistent slab engine.
