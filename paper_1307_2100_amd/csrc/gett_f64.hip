@@ -140,6 +140,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_dma_kernel(GettParams
   const double* const A = p.A + off_at(p.aL, l);
   const double* const B = p.B + off_at(p.bL, l);
   const int64_t K = p.K;
+  // the wavefront index as a uniform value: a copy's LDS address (M0) is then
+  // scalar arithmetic
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
   const int64_t sa0 = dk.sa[0], sb0 = dk.sb[0];
   // offset of contracted index k in the kernel's A (koff_a) or B (koff_b)
   auto koff_a = [&](int64_t k) -> int64_t {
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_dma_kernel(GettParams
   const bool whole = dk.ext[0] % BK == 0;
   // copy j of tile t, uniform contracted offsets (whole first mode, tile in range)
   auto copy_fast = [&](int j, int64_t ta, int64_t tb, int stage) {
-    const int c = wave + NW * j;
+    const int c = wave_u + NW * j;
     const bool opb = c >= 2 * ABLK;
     __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(base[j] + (opb ? tb : ta)),
                                      (void __attribute__((address_space(3)))*)(dsm + stage * STAGE + c * 1024), 16,
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gett_f64_dma_kernel(GettParams
   };
   // copy j of tile t with this lane's own contracted digits (clamped to K)
   auto copy_slow = [&](int j, int64_t t, int stage) {
-    const int c = wave + NW * j;
+    const int c = wave_u + NW * j;
     const bool opb = c >= 2 * ABLK;
     const int h = c & 1;
     const bool kf = opb ? BKF : AKF;
