@@ -1086,10 +1086,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void crt_gemm_dma_kernel(CrtGemmArg
     const int q = lane >> 4;
     src[j] = (r < BM ? r : r - BM) * BK + q * 16;
   }
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);  // uniform: LDS addresses in scalar arithmetic
   auto issue = [&](int64_t ks, int stage) {
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
-      const int c = wave + NW * j;
+      const int c = wave_u + NW * j;
       const signed char* base = 16 * c < BM ? PA + ks * kstepA : PB + ks * kstepB;
       __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(base + src[j]),
                                        (void __attribute__((address_space(3)))*)(dsm + stage * STAGE + c * 1024),
