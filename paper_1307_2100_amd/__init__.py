@@ -48,7 +48,7 @@ RECIPES = {"auto": 0, "gemm": 1, "copy_gemm": 2, "gemv": 3, "ger": 4, "dot": 5}
 RECIPE_NAMES = {v: k for k, v in RECIPES.items()}
 KERNEL_NAMES = {0: "mfma_gemm", 1: "lanes_over_outputs", 2: "lanes_over_k", 3: "batched_small", 4: "split"}
 # GEMM tile configurations compiled into libtc (ids 0 .. NUM_TILES-1)
-NUM_TILES = 18
+NUM_TILES = 20
 # tc_picker
 TC_PICKER_RULES, TC_PICKER_MLP, TC_PICKER_TUNED = 0, 1, 2
 PICKERS = {"rules": 0, "mlp": 1, "tuned": 2}

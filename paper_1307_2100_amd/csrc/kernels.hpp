@@ -118,7 +118,9 @@ struct GettParams {
   X(14, 32, 32, 64, 2, 2)     \
   X(15, 64, 64, 32, 2, 2)     \
   X(16, 32, 32, 128, 2, 2)    \
-  X(17, 64, 64, 64, 2, 2)
+  X(17, 64, 64, 64, 2, 2)      \
+  X(18, 128, 32, 16, 4, 1)     \
+  X(19, 32, 128, 16, 1, 4)
 struct TileCfg {
   int id, bm, bn, bk, wgm, wgn;
 };

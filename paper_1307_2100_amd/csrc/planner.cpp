@@ -201,9 +201,13 @@ int pick_tile(int64_t M, int64_t N, int64_t K, int64_t L) {
     // under a quarter of their area on padding and split-K (below 128 tiles)
     // turns them into at least 256 workgroups.  Larger tiles would leave each
     // segment too few k-steps; smaller ones stage too little per byte.
-    // A narrow column range (at most 48) beside a long row range: 128 x 64
-    // tiles with split-K (measured ahead of 32 x 32 and 64 x 64 tiles on the
-    // coupled-cluster shapes with short indices of 30 and 45).
+    // A narrow column range beside a long row range: 128 x 32 tiles when it
+    // is at most 32 wide, 128 x 64 when at most 48 (and the same transposed
+    // for a narrow row range), with split-K (measured ahead of 32 x 32 and
+    // 64 x 64 tiles on the coupled-cluster shapes with short indices of 30
+    // and 45).
+    if (N <= 32 && M >= 512 && tiles(128, 32) < 128) return 18;
+    if (M <= 32 && N >= 512 && tiles(32, 128) < 128) return 19;
     if (N <= 48 && M >= 512 && tiles(128, 64) < 128) return 2;
     for (int id : {9, 1}) {
       const TileCfg& t = kTiles[id];

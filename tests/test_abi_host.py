@@ -375,8 +375,10 @@ def test_fast_division_method():
 
 
 def test_long_contracted_range_tile_rule():
-    """Few output tiles over a long contracted range: the rules take 128x64
-    tiles for a column range of at most 48 beside a long row range, else
+    """Few output tiles over a long contracted range: the rules take 128x32
+    tiles for a column range of at most 32 beside a long row range (32x128
+    for a row range of at most 32), 128x64 tiles for a column range of at
+    most 48, else
     128x128 tiles, else 64x64, when padding wastes under a quarter of the tile and
     split-K turns them into 256 or more workgroups; failing that they still
     move from 32x32 tiles (no split-K at 128 tiles or more) to 64x64 or
@@ -384,7 +386,8 @@ def test_long_contracted_range_tile_rule():
     for (m, k, n), tile in (((384, 147456, 384), 9), ((512, 262144, 512), 9), ((192, 36864, 192), 1),
                             ((3600, 10 ** 6, 60), 1), ((2025, 10 ** 6, 45), 1), ((1000, 3000, 1000), 9),
                             ((256, 10000, 256), 1), ((383, 2100, 390), 1), ((777, 2100, 700), 9),
-                            ((30, 10 ** 6, 900), 2), ((45, 10 ** 6, 2025), 2)):
+                            ((30, 10 ** 6, 900), 18), ((900, 10 ** 6, 30), 19), ((45, 10 ** 6, 2025), 2),
+                            ((33, 10 ** 6, 900), 2)):
         info = analyze("ak", "kb", "ab", {"a": m, "k": k, "b": n})
         assert info.tile_id == tile and info.k_split > 1, (m, k, n, info.tile_id)
     # short range or enough tiles: unchanged

@@ -258,8 +258,10 @@ def test_suggested_layout_runs_as_direct_gemm(case):
 @pytest.mark.parametrize("ext,tile,forced", [
     ({"a": 383, "k": 2100, "b": 390}, 1, False),   # the rules: 64x64 tiles + split-K
     ({"a": 777, "k": 2100, "b": 700}, 9, False),   # the rules: 128x128 tiles + split-K
-    ({"a": 30, "k": 2100, "b": 600}, 2, False),    # the rules' narrow-column case: 128x64 tiles + split-K,
-                                                   # one ragged column tile of 30 < 64
+    ({"a": 30, "k": 2100, "b": 600}, 18, False),   # the rules' narrow-column case: 128x32 tiles + split-K,
+                                                   # one ragged column tile of 30 < 32
+    ({"a": 600, "k": 2100, "b": 30}, 19, False),   # narrow rows: 32x128 tiles + split-K
+    ({"a": 40, "k": 2100, "b": 600}, 2, False),    # a column range of 33..48: 128x64 tiles + split-K
     ({"a": 500, "k": 8192, "b": 510}, 11, True),   # split-K on the largest tiles, ragged edges
     ({"a": 380, "k": 8192, "b": 380}, 12, True),
     ({"a": 380, "k": 4096, "b": 380}, 5, True),
