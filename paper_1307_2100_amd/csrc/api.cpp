@@ -1148,7 +1148,8 @@ tc_status tc_batch_create(tc_batch_t* out, int n, const tc_plan_t* plans) {
       } else {
         // inner products over a contracted group of several modes address
         // it through block tables
-        const bool kblk = an.kernel == tc::Analysis::KERNEL_LANES_K && an.g[tc::GK].n >= 2 && !an.empty_out;
+        const bool kblk = an.kernel == tc::Analysis::KERNEL_LANES_K && an.g[tc::GK].n >= 2 && !an.empty_out &&
+                          an.g[tc::GK].size() > 0;  // an empty sum keeps the plain (empty) tables
         build_tables(an, OffsTargets{&it.g.aM, &it.g.aK, &it.g.aL, &it.g.bN, &it.g.bK, &it.g.bL, &it.g.cM, &it.g.cN,
                                      &it.g.cL},
                      host, pos, kblk);

@@ -26,7 +26,11 @@ def _make_batch(count, seed, kind="integers"):
              ("ki", "k", "i", {"k": 40000, "i": 7}),                             # lanes over k, 3 segments
              ("kb", "kb", "b", {"k": 50000, "b": 3}),                            # inner products per b
              ("ik", "k", "i", {"i": 300, "k": 3000}),                            # lanes over outputs, segments
-             ("ik", "kj", "ij", {"i": 600, "k": 300, "j": 1})]
+             ("ik", "kj", "ij", {"i": 600, "k": 300, "j": 1}),
+             # inner products over two contracted modes whose stride-1 modes differ (block tables,
+             # ragged blocks), and the same with a zero extent (an empty sum: plain tables)
+             ("kmi", "mki", "i", {"k": 37, "m": 30, "i": 3}),
+             ("kmi", "mki", "i", {"k": 0, "m": 30, "i": 3})]
     for _ in range(count):
         specs.append(synth.random_contraction(g, rank_range=(3, 6), ext_range=(2, 9), max_elems=20000,
                                               p_outer=0.03, allow_batch=True))
